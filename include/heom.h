@@ -1,0 +1,188 @@
+/* heom.h -- C-ABI of the MI355X (gfx950) HEOM propagation library, libheom.so.
+ *
+ * The library propagates the hierarchical equations of motion of
+ * Kreisbeck, Kramer, Rodriguez and Hein (arXiv:1012.4382) for an N-site
+ * Frenkel exciton system (section "Model", eq. H_ex) whose sites couple
+ * linearly to independent Drude-Lorentz phonon baths (eq:gamma), with
+ * trapping and recombination sinks treated in the Born-Markov limit
+ * (eq:lab2, eq:lab3; hybrid "ME-HEOM" of Appendix A), by classic fourth-order
+ * Runge-Kutta (Appendix B).  The hierarchy is eq:labsevena / eq:lab8,
+ * truncated at depth N_max = sum_m n_m (text after eq:lab8); its size is
+ * C(M + D, D) for M bath modes (Appendix B).
+ *
+ * Conventions for every entry point:
+ *   - All functions except heom_destroy return a status (HEOM_OK or one of the
+ *     negative codes below).  On HEOM_E_INVALID nothing has been written.
+ *     heom_last_error() returns a thread-local message for the last failure.
+ *   - No C++ exception crosses this interface.
+ *   - Host arrays are owned by the caller and only read (or, for outputs,
+ *     written) during the call; the library keeps copies of what it needs.
+ *   - Complex numbers are interleaved (re, im) doubles; matrices are row-major.
+ *   - Device workspaces are owned by the caller (any device allocation of at
+ *     least the stated size, 256-byte aligned); the library never frees them.
+ *     The state of a run lives entirely in its workspace, so a run can be
+ *     continued with HEOM_RESUME.  Calls that use one workspace must not
+ *     overlap; distinct workspaces and streams may be used concurrently with
+ *     one hierarchy handle, which is immutable after it is built.
+ *   - Calls that return host data synchronise their stream before returning.
+ *   - Units: energies in cm^-1, times in fs, temperatures in K, rates in 1/ps.
+ *     Internally hbar = 1 and energies become angular frequencies in rad/fs.
+ */
+#ifndef HEOM_H
+#define HEOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  HEOM_OK = 0,
+  HEOM_E_INVALID = -1,     /* an argument failed validation                     */
+  HEOM_E_NOMEM = -2,       /* host or device allocation failed                  */
+  HEOM_E_DEVICE = -3,      /* a HIP runtime call failed (text in last error)    */
+  HEOM_E_NUMERIC = -4,     /* NaN/Inf in the reduced density matrix             */
+  HEOM_E_WORKSPACE = -5,   /* workspace missing, too small or misaligned        */
+  HEOM_E_UNSUPPORTED = -6  /* valid request this build cannot serve             */
+};
+
+/* Precision of the bulk ADO update.  HEOM_FP32_MIXED stores and updates every
+ * sigma_n with n != 0 in FP32; sigma_0 (the reduced density matrix), its
+ * update, the sink integrals and the recorded history stay FP64. */
+enum { HEOM_FP64 = 0, HEOM_FP32_MIXED = 1 };
+
+/* Flags for heom_propagate / heom_propagate_batch. */
+enum {
+  HEOM_RESUME = 1,          /* continue from the state held in the workspace   */
+  HEOM_GENERIC_KERNEL = 2   /* diagnostic: use the generic stage kernel even
+                               where a specialised one exists                   */
+};
+
+typedef struct heom_hierarchy heom_hierarchy; /* opaque, library-owned */
+
+/* Physical system (section "Model" and Appendix A of the paper). */
+typedef struct {
+  int32_t n_sites;                 /* N, 1 <= N <= 64                               */
+  const double *hamiltonian_cm;    /* N*N complex, Hermitian (to 1e-12 max|H|), cm^-1;
+                                      site energies on the diagonal (eq. H_ex)      */
+  const double *lambda_cm;         /* [N] reorganisation energies, >= 0, cm^-1      */
+  const double *gamma_inv_fs;      /* [N] bath correlation times 1/gamma, > 0, fs   */
+  double temperature_K;            /* > 0                                           */
+  int32_t n_matsubara;             /* K >= 0 Matsubara terms per bath               */
+  int32_t low_temp_correction;     /* 1: Markovian residual of the Matsubara tail
+                                      beyond K on every ADO; 0: none               */
+  int32_t theta_form;              /* 0: Drude amplitude lambda*gamma*(cot(gamma/2kT) - i);
+                                      1: the paper's high-temperature
+                                      2*lambda*kT - i*lambda*gamma                 */
+  const double *trap_rate_per_ps;  /* [N] trapping rate to the reaction centre
+                                      per site (eq:lab3), or NULL for none         */
+  const double *recomb_rate_per_ps;/* [N] recombination rate to the ground state
+                                      per site (eq:lab2), or NULL for none         */
+} heom_system;
+
+/* Result of heom_efficiency (eq:eta, eq:trappingtime). */
+typedef struct {
+  double eta;               /* P_trap(t_end): population trapped in the reaction centre */
+  double mean_trap_time_fs; /* int_0^t_end t dP_trap(t), eq:trappingtime               */
+  double p_recomb;          /* population lost to the ground state by t_end           */
+  double p_remaining;       /* Tr sigma_0(t_end): population still on the sites       */
+  double t_end_fs;          /* time actually reached                                  */
+} heom_eff_result;
+
+/* Builds the hierarchy for `sys` truncated at depth `depth` (>= 0): bath modes
+ * and amplitudes from eq:gamma and its Matsubara expansion, the multi-index
+ * map of every ADO with |n| <= depth, and the neighbour tables n +- e_m
+ * (Appendix B: each matrix is linked to its neighbours).  Host-only work; the
+ * tables are copied to a device on first use there.
+ * Errors: HEOM_E_INVALID (see the field comments; also a Matsubara frequency
+ * within 1e-9 relative of gamma, or more than 2^31 - 1 ADOs), HEOM_E_NOMEM.
+ * On success *out owns the handle; release it with heom_destroy. */
+int heom_build_hierarchy(const heom_system *sys, int32_t depth, heom_hierarchy **out);
+
+/* Sizes of a built hierarchy.  Any output pointer may be NULL.
+ *   n_ados      number of ADOs, C(M + depth, depth)
+ *   n_modes     M = N * (K + 1)
+ *   workspace_bytes_fp64 / _fp32   workspace needed by heom_propagate */
+int heom_hierarchy_info(const heom_hierarchy *h, int64_t *n_ados, int32_t *n_modes,
+                        size_t *workspace_bytes_fp64, size_t *workspace_bytes_fp32);
+
+/* Copies the hierarchy description to host arrays (any may be NULL):
+ *   multi [n_ados][M]  multi-index of each ADO in the library's order
+ *   up    [n_ados][M]  index of n + e_m, or -1 beyond the truncation
+ *   down  [n_ados][M]  index of n - e_m, or -1 where n_m = 0 */
+int heom_hierarchy_tables(const heom_hierarchy *h, int32_t *multi, int32_t *up, int32_t *down);
+
+/* Bath modes in mode order m = site * (K + 1) + k (k = 0 is the Drude term):
+ * site[m], amplitude c_m = c_re + i c_im (rad/fs^2) and rate nu_m (1/fs) of the
+ * correlation function sum_m c_m exp(-nu_m t), and the correction residual
+ * delta[N] (rad/fs).  Any pointer may be NULL. */
+int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, double *c_im,
+                         double *nu, double *delta);
+
+/* Propagates rho0 by n_steps RK4 steps of dt_fs on the current device.
+ *   precision      HEOM_FP64 or HEOM_FP32_MIXED
+ *   flags          HEOM_RESUME: continue the run held in d_workspace (rho0 is
+ *                  then ignored and may be NULL); HEOM_GENERIC_KERNEL
+ *   rho0           [N][N] complex Hermitian initial reduced density matrix;
+ *                  every deeper ADO starts at zero (text after eq:lab8)
+ *   record_every   >= 1; rho is recorded at step 0 and every record_every steps
+ *   d_workspace    device memory of at least workspace_bytes_* for `precision`
+ *   hip_stream     hipStream_t to run on, NULL for the default stream
+ *   rho_out        host [(n_steps / record_every) + 1][N][N] complex, or NULL
+ *   sinks_out      host [3] = {P_trap, P_recomb, Q = int_0^t P_trap dt'} after
+ *                  the last step, or NULL
+ * Errors: HEOM_E_INVALID, HEOM_E_WORKSPACE, HEOM_E_DEVICE, HEOM_E_NUMERIC
+ * (NaN/Inf in a recorded rho; the run stops there). */
+int heom_propagate(heom_hierarchy *h, int precision, int flags, const double *rho0, double dt_fs,
+                   int64_t n_steps, int64_t record_every, void *d_workspace,
+                   size_t workspace_bytes, void *hip_stream, double *rho_out, double *sinks_out);
+
+/* Workspace needed to propagate the n hierarchies hs[] together. */
+int heom_batch_workspace_bytes(heom_hierarchy *const *hs, int32_t n, int precision,
+                               size_t *bytes);
+
+/* Propagates n independent instances with one kernel launch per RK4 stage
+ * (per distinct kernel variant), all with the same dt_fs, n_steps and
+ * record_every.  rho0s[i], rho_outs[i] and sinks_outs[i] are as in
+ * heom_propagate for instance i (rho_outs / sinks_outs may be NULL, or hold
+ * NULL entries).  Each instance's arithmetic does not depend on the others:
+ * results equal those of heom_propagate on the instance alone. */
+int heom_propagate_batch(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
+                         const double *const *rho0s, double dt_fs, int64_t n_steps,
+                         int64_t record_every, void *d_workspace, size_t workspace_bytes,
+                         void *hip_stream, double *const *rho_outs, double *const *sinks_outs);
+
+/* Energy-transfer efficiency (eq:eta) and mean trapping time (eq:trappingtime)
+ * for an excitation starting in rho0.
+ *   t_end_fs > 0   propagate to this fixed time (rounded to whole steps)
+ *   t_end_fs <= 0  propagate until the population left on the sites drops
+ *                  below pop_tol (the paper's t_max criterion, 1e-5 there)
+ * Errors as heom_propagate; HEOM_E_NUMERIC also when the criterion is not met
+ * within 10^8 steps. */
+int heom_efficiency(heom_hierarchy *h, int precision, const double *rho0, double dt_fs,
+                    double t_end_fs, double pop_tol, void *d_workspace, size_t workspace_bytes,
+                    void *hip_stream, heom_eff_result *out);
+
+/* Copies the full state held in a workspace to the host:
+ * state_out [n_ados][N][N] complex (library order, full Hermitian matrices)
+ * followed by 3 doubles {P_trap, P_recomb, Q}.  Synchronises hip_stream. */
+int heom_read_state(const heom_hierarchy *h, int precision, const void *d_workspace,
+                    size_t workspace_bytes, void *hip_stream, double *state_out);
+
+/* Releases a handle and its device tables.  NULL is accepted. */
+void heom_destroy(heom_hierarchy *h);
+
+/* Static text for a status code. */
+const char *heom_status_string(int status);
+
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *heom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEOM_H */

@@ -1,0 +1,125 @@
+// heom_internal.h -- structures shared by the host sources and the HIP kernels
+// of libheom.so.  Not part of the public interface (include/heom.h).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "heom.h"
+
+#ifdef __HIP__
+#define HEOM_HD __host__ __device__
+#else
+#define HEOM_HD
+#endif
+
+namespace heom {
+
+constexpr int kMaxSites = 64;
+// Records of sigma_0 held on the device between copies to the host.
+constexpr int64_t kRingRecords = 512;
+// ADOs are padded to a multiple of this in every plane (one wave of lanes).
+constexpr int64_t kPlanePad = 64;
+
+// Layout of one ADO ("packed Hermitian", N*N reals): plane e < N holds the
+// real diagonal entry (e, e); for each pair a < b in row-major order, with pair
+// index p, plane N + 2p holds Re sigma_ab and plane N + 2p + 1 holds Im sigma_ab.
+// Element e of ADO i lives at plane[e * stride + i] (structure of arrays), so
+// lanes that handle consecutive ADOs read consecutive addresses.
+HEOM_HD inline int pair_index(int N, int a, int b) {  // a < b
+  return a * N - a * (a + 1) / 2 + (b - a - 1);
+}
+
+// Per-instance parameters, all converted to rad/fs (energies) and 1/fs
+// (rates), laid out as one array of doubles in the workspace:
+//   [0, N^2)           H_re (diagonal offset removed)
+//   [N^2, 2N^2)        H_im
+//   [2N^2, +N)         decay: (trap_a + rec_a) / 2
+//   [.., +N)           delta_a (low-temperature correction residual)
+//   [.., +N)           trap_a
+//   [.., +N)           rec_a
+//   [.., +M)           Re c_m
+//   [.., +M)           Im c_m
+//   [.., +M)           nu_m
+//   [.., +N*N)         packed rho0 (used by the initialisation kernel)
+struct ParamOffsets {
+  int h_re, h_im, half_gamma, delta, trap, rec, c_re, c_im, nu, rho0, total;
+};
+HEOM_HD inline ParamOffsets param_offsets(int N, int M) {
+  ParamOffsets o;
+  o.h_re = 0;
+  o.h_im = N * N;
+  o.half_gamma = 2 * N * N;
+  o.delta = o.half_gamma + N;
+  o.trap = o.delta + N;
+  o.rec = o.trap + N;
+  o.c_re = o.rec + N;
+  o.c_im = o.c_re + M;
+  o.nu = o.c_im + M;
+  o.rho0 = o.nu + M;
+  o.total = o.rho0 + N * N;
+  return o;
+}
+
+// Scalars carried with each state buffer: P_trap, P_rec, Q = int P_trap dt.
+constexpr int kScalars = 4;  // padded
+
+// Device descriptor of one instance (lives in the workspace).
+struct InstDesc {
+  void *y, *a, *b;            // planes of the state and the two stage buffers (T*)
+  double *y0, *a0, *b0;       // FP64 sigma_0 copies (mixed precision only)
+  double *sc_y, *sc_a, *sc_b; // kScalars each
+  double *hist;               // kRingRecords x (N*N + kScalars)
+  const double *params;       // see ParamOffsets
+  const int32_t *up, *down;   // [M][stride]
+  const uint8_t *occ;         // [M][stride]
+  int64_t n_ados, stride;
+  int32_t N, M, KP, pad_;
+};
+
+// A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
+struct WorkItem {
+  int32_t inst;
+  int32_t first;
+};
+
+}  // namespace heom
+
+// Host-side hierarchy handle.
+struct heom_hierarchy {
+  int N = 0, K = 0, KP = 1, M = 0, depth = 0;
+  int64_t n_ados = 0, stride = 0;
+  bool h_real = true;
+  double energy_offset = 0.0;  // removed mean site energy, rad/fs
+  std::vector<double> params;  // ParamOffsets layout without rho0 filled
+  std::vector<int32_t> site;   // [M]
+  std::vector<double> c_re, c_im, nu, delta;
+  std::vector<int32_t> multi;  // [n_ados][M]
+  std::vector<int32_t> up, down;  // [M][stride] (device layout)
+  std::vector<uint8_t> occ;       // [M][stride]
+  // Device copies of the tables, per device ordinal.
+  struct DeviceTables {
+    int device = -1;
+    int32_t *up = nullptr, *down = nullptr;
+    uint8_t *occ = nullptr;
+  };
+  mutable std::mutex mu;
+  mutable std::vector<DeviceTables> dev;
+};
+
+namespace heom {
+
+// Thread-local error text.
+void set_error(const std::string &msg);
+int fail(int status, const std::string &msg);
+
+// params.cpp
+int build_params(const heom_system *sys, heom_hierarchy *h);
+// hierarchy.cpp
+int build_tables(heom_hierarchy *h);
+
+}  // namespace heom

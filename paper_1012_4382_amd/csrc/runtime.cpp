@@ -1,0 +1,662 @@
+// runtime.cpp -- C-ABI entry points of libheom.so (host side).
+//
+// Builds hierarchies (params.cpp, hierarchy.cpp), lays out caller-owned device
+// workspaces, uploads per-instance parameters and neighbour tables, and
+// sequences the RK4 stage kernels (stage_kernels.hip) with the sigma_0
+// history ring that is copied to the host in chunks (the paper keeps every
+// ADO on the device and moves only the N x N reduced density matrix,
+// Appendix B).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "heom_internal.h"
+
+namespace heom {
+
+// stage_kernels.hip
+bool has_fixed_kernel(int N, int KP);
+hipError_t launch_stage(bool fixed, bool mixed, int N, int KP, const InstDesc *descs,
+                        const WorkItem *work, int n_items, int block, int stage, double coef,
+                        int hist_slot, hipStream_t stream);
+hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
+                       int block, hipStream_t stream);
+hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
+                           hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr uint64_t kMagic = 0x48454f4d57530001ull;  // "HEOMWS" v1
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int dev_fail(hipError_t e, const char *what) {
+  return fail(HEOM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HEOM_HIP(call, what)                      \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return dev_fail(e_, what); \
+  } while (0)
+
+// ADOs handled by one workgroup (one lane per ADO).
+int block_ados() {
+  static int v = [] {
+    const char *s = std::getenv("HEOM_BLOCK_ADOS");
+    int b = s ? std::atoi(s) : 128;
+    if (b != 64 && b != 128 && b != 256) b = 128;
+    return b;
+  }();
+  return v;
+}
+
+struct Header {
+  uint64_t magic;
+  int64_t n_inst;
+  int64_t precision;
+  int64_t total_ados;
+};
+
+struct InstLayout {
+  size_t params, y, a, b, y0, a0, b0, sc_y, sc_a, sc_b, hist;
+};
+
+struct Layout {
+  size_t header = 0, descs = 0, work = 0;
+  int64_t work_cap = 0;
+  std::vector<InstLayout> inst;
+  size_t total = 0;
+};
+
+Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
+  Layout L;
+  size_t off = 0;
+  L.header = off;
+  off = align_up(off + sizeof(Header));
+  L.descs = off;
+  off = align_up(off + sizeof(InstDesc) * n);
+  int64_t cap = 0;
+  for (int k = 0; k < n; ++k) cap += (hs[k]->n_ados + kPlanePad - 1) / kPlanePad;
+  L.work = off;
+  L.work_cap = cap;
+  off = align_up(off + sizeof(WorkItem) * cap);
+  const size_t elt = (precision == HEOM_FP32_MIXED) ? 4 : 8;
+  L.inst.resize(n);
+  for (int k = 0; k < n; ++k) {
+    const heom_hierarchy *h = hs[k];
+    const size_t N2 = static_cast<size_t>(h->N) * h->N;
+    InstLayout &I = L.inst[k];
+    I.params = off;
+    off = align_up(off + sizeof(double) * param_offsets(h->N, h->M).total);
+    const size_t plane_bytes = elt * N2 * static_cast<size_t>(h->stride);
+    I.y = off;
+    off = align_up(off + plane_bytes);
+    I.a = off;
+    off = align_up(off + plane_bytes);
+    I.b = off;
+    off = align_up(off + plane_bytes);
+    I.y0 = off;
+    off = align_up(off + sizeof(double) * N2);
+    I.a0 = off;
+    off = align_up(off + sizeof(double) * N2);
+    I.b0 = off;
+    off = align_up(off + sizeof(double) * N2);
+    I.sc_y = off;
+    off = align_up(off + sizeof(double) * kScalars);
+    I.sc_a = off;
+    off = align_up(off + sizeof(double) * kScalars);
+    I.sc_b = off;
+    off = align_up(off + sizeof(double) * kScalars);
+    I.hist = off;
+    off = align_up(off + sizeof(double) * (N2 + kScalars) * kRingRecords);
+  }
+  L.total = off;
+  return L;
+}
+
+int ensure_device_tables(const heom_hierarchy *h, int device, heom_hierarchy::DeviceTables *out) {
+  std::lock_guard<std::mutex> lock(h->mu);
+  for (const auto &t : h->dev)
+    if (t.device == device) {
+      *out = t;
+      return HEOM_OK;
+    }
+  heom_hierarchy::DeviceTables t;
+  t.device = device;
+  const size_t n32 = h->up.size() * sizeof(int32_t);
+  const size_t n8 = h->occ.size();
+  hipError_t e;
+  if ((e = hipMalloc(reinterpret_cast<void **>(&t.up), n32)) != hipSuccess)
+    return dev_fail(e, "hipMalloc(tables)");
+  if ((e = hipMalloc(reinterpret_cast<void **>(&t.down), n32)) != hipSuccess) {
+    (void)hipFree(t.up);
+    return dev_fail(e, "hipMalloc(tables)");
+  }
+  if ((e = hipMalloc(reinterpret_cast<void **>(&t.occ), n8)) != hipSuccess) {
+    (void)hipFree(t.up);
+    (void)hipFree(t.down);
+    return dev_fail(e, "hipMalloc(tables)");
+  }
+  if ((e = hipMemcpy(t.up, h->up.data(), n32, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(t.down, h->down.data(), n32, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(t.occ, h->occ.data(), n8, hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(t.up);
+    (void)hipFree(t.down);
+    (void)hipFree(t.occ);
+    return dev_fail(e, "hipMemcpy(tables)");
+  }
+  h->dev.push_back(t);
+  *out = t;
+  return HEOM_OK;
+}
+
+// Packs a Hermitian N x N complex matrix into N*N reals (plane order).
+int pack_hermitian(int N, const double *rho, double *packed) {
+  double mx = 0.0;
+  for (int k = 0; k < 2 * N * N; ++k) {
+    if (!std::isfinite(rho[k])) return fail(HEOM_E_INVALID, "rho0 has a non-finite entry");
+    mx = std::fmax(mx, std::fabs(rho[k]));
+  }
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      const double dr = rho[2 * (a * N + b)] - rho[2 * (b * N + a)];
+      const double di = rho[2 * (a * N + b) + 1] + rho[2 * (b * N + a) + 1];
+      if (std::fabs(dr) > 1e-12 * mx || std::fabs(di) > 1e-12 * mx)
+        return fail(HEOM_E_INVALID, "rho0 is not Hermitian");
+    }
+  for (int a = 0; a < N; ++a) packed[a] = rho[2 * (a * N + a)];
+  for (int a = 0; a < N; ++a)
+    for (int b = a + 1; b < N; ++b) {
+      const int e = N + 2 * pair_index(N, a, b);
+      packed[e] = rho[2 * (a * N + b)];
+      packed[e + 1] = rho[2 * (a * N + b) + 1];
+    }
+  return HEOM_OK;
+}
+
+void unpack_hermitian(int N, const double *packed, double *rho) {
+  for (int a = 0; a < N; ++a) {
+    rho[2 * (a * N + a)] = packed[a];
+    rho[2 * (a * N + a) + 1] = 0.0;
+    for (int b = a + 1; b < N; ++b) {
+      const int e = N + 2 * pair_index(N, a, b);
+      rho[2 * (a * N + b)] = packed[e];
+      rho[2 * (a * N + b) + 1] = packed[e + 1];
+      rho[2 * (b * N + a)] = packed[e];
+      rho[2 * (b * N + a) + 1] = -packed[e + 1];
+    }
+  }
+}
+
+struct Group {
+  bool fixed;
+  int N, KP;
+  int64_t item_begin, n_items;
+};
+
+int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
+                   const double *const *rho0s, double dt_fs, int64_t n_steps, int64_t record_every,
+                   void *d_ws, size_t ws_bytes, void *hip_stream, double *const *rho_outs,
+                   double *const *sinks_outs) {
+  if (!hs || n < 1) return fail(HEOM_E_INVALID, "no hierarchies");
+  for (int k = 0; k < n; ++k)
+    if (!hs[k]) return fail(HEOM_E_INVALID, "NULL hierarchy handle");
+  if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
+    return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
+  if (flags & ~(HEOM_RESUME | HEOM_GENERIC_KERNEL)) return fail(HEOM_E_INVALID, "unknown flags");
+  if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
+  if (n_steps < 0) return fail(HEOM_E_INVALID, "n_steps must be >= 0");
+  if (record_every < 1) return fail(HEOM_E_INVALID, "record_every must be >= 1");
+  const bool resume = (flags & HEOM_RESUME) != 0;
+  const bool mixed = precision == HEOM_FP32_MIXED;
+  const Layout L = make_layout(hs, n, precision);
+  if (!d_ws) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+    return fail(HEOM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(HEOM_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  // Packed initial states (validated before any device work).
+  std::vector<std::vector<double>> params(n);
+  for (int k = 0; k < n; ++k) {
+    params[k] = hs[k]->params;
+    if (!resume) {
+      if (!rho0s || !rho0s[k]) return fail(HEOM_E_INVALID, "rho0 is NULL");
+      const ParamOffsets o = param_offsets(hs[k]->N, hs[k]->M);
+      int rc = pack_hermitian(hs[k]->N, rho0s[k], params[k].data() + o.rho0);
+      if (rc) return rc;
+    }
+  }
+
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  int device = 0;
+  HEOM_HIP(hipGetDevice(&device), "hipGetDevice");
+  char *ws = static_cast<char *>(d_ws);
+
+  // Descriptors and work list.
+  std::vector<InstDesc> descs(n);
+  for (int k = 0; k < n; ++k) {
+    heom_hierarchy::DeviceTables t;
+    int rc = ensure_device_tables(hs[k], device, &t);
+    if (rc) return rc;
+    const InstLayout &I = L.inst[k];
+    InstDesc &d = descs[k];
+    d.y = ws + I.y;
+    d.a = ws + I.a;
+    d.b = ws + I.b;
+    d.y0 = reinterpret_cast<double *>(ws + I.y0);
+    d.a0 = reinterpret_cast<double *>(ws + I.a0);
+    d.b0 = reinterpret_cast<double *>(ws + I.b0);
+    d.sc_y = reinterpret_cast<double *>(ws + I.sc_y);
+    d.sc_a = reinterpret_cast<double *>(ws + I.sc_a);
+    d.sc_b = reinterpret_cast<double *>(ws + I.sc_b);
+    d.hist = reinterpret_cast<double *>(ws + I.hist);
+    d.params = reinterpret_cast<const double *>(ws + I.params);
+    d.up = t.up;
+    d.down = t.down;
+    d.occ = t.occ;
+    d.n_ados = hs[k]->n_ados;
+    d.stride = hs[k]->stride;
+    d.N = hs[k]->N;
+    d.M = hs[k]->M;
+    d.KP = hs[k]->KP;
+    d.pad_ = 0;
+  }
+  const bool allow_fixed = (flags & HEOM_GENERIC_KERNEL) == 0;
+  const int block = block_ados();
+  std::map<std::tuple<bool, int, int>, std::vector<int>> by_key;
+  for (int k = 0; k < n; ++k) {
+    const heom_hierarchy *h = hs[k];
+    const bool fixed = allow_fixed && h->h_real && has_fixed_kernel(h->N, h->KP);
+    by_key[std::make_tuple(fixed, h->N, fixed ? h->KP : 0)].push_back(k);
+  }
+  std::vector<WorkItem> items;
+  std::vector<Group> groups;
+  for (const auto &kv : by_key) {
+    Group g;
+    g.fixed = std::get<0>(kv.first);
+    g.N = std::get<1>(kv.first);
+    g.KP = g.fixed ? std::get<2>(kv.first) : 0;
+    g.item_begin = static_cast<int64_t>(items.size());
+    for (int k : kv.second)
+      for (int64_t first = 0; first < hs[k]->n_ados; first += block)
+        items.push_back({k, static_cast<int32_t>(first)});
+    g.n_items = static_cast<int64_t>(items.size()) - g.item_begin;
+    groups.push_back(g);
+  }
+  if (static_cast<int64_t>(items.size()) > L.work_cap)
+    return fail(HEOM_E_WORKSPACE, "work list exceeds its workspace region");
+
+  int64_t total_ados = 0;
+  for (int k = 0; k < n; ++k) total_ados += hs[k]->n_ados;
+  Header hdr = {kMagic, n, precision, total_ados};
+  if (resume) {
+    Header cur;
+    HEOM_HIP(hipMemcpyAsync(&cur, ws + L.header, sizeof(Header), hipMemcpyDeviceToHost, stream),
+             "hipMemcpyAsync(header)");
+    HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (std::memcmp(&cur, &hdr, sizeof(Header)) != 0)
+      return fail(HEOM_E_WORKSPACE, "workspace does not hold a run of these hierarchies");
+  }
+  HEOM_HIP(hipMemcpyAsync(ws + L.descs, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice,
+                          stream),
+           "hipMemcpyAsync(descs)");
+  HEOM_HIP(hipMemcpyAsync(ws + L.work, items.data(), sizeof(WorkItem) * items.size(),
+                          hipMemcpyHostToDevice, stream),
+           "hipMemcpyAsync(work)");
+  for (int k = 0; k < n; ++k)
+    HEOM_HIP(hipMemcpyAsync(ws + L.inst[k].params, params[k].data(),
+                            sizeof(double) * params[k].size(), hipMemcpyHostToDevice, stream),
+             "hipMemcpyAsync(params)");
+  const InstDesc *d_descs = reinterpret_cast<const InstDesc *>(ws + L.descs);
+  const WorkItem *d_work = reinterpret_cast<const WorkItem *>(ws + L.work);
+  if (!resume) {
+    HEOM_HIP(launch_init(mixed, d_descs, d_work, static_cast<int>(items.size()), block, stream),
+             "init kernel");
+    HEOM_HIP(hipMemcpyAsync(ws + L.header, &hdr, sizeof(Header), hipMemcpyHostToDevice, stream),
+             "hipMemcpyAsync(header)");
+  }
+
+  bool want_rho = false;
+  for (int k = 0; rho_outs && k < n; ++k) want_rho = want_rho || rho_outs[k] != nullptr;
+  std::vector<std::vector<double>> host_ring(n);
+  int slot = 0;
+  int64_t rec_done = 0;
+  auto drain = [&]() -> int {
+    if (slot == 0) return HEOM_OK;
+    for (int k = 0; k < n; ++k) {
+      if (!rho_outs[k]) continue;
+      const size_t rec_len = static_cast<size_t>(hs[k]->N) * hs[k]->N + kScalars;
+      host_ring[k].resize(rec_len * slot);
+      HEOM_HIP(hipMemcpyAsync(host_ring[k].data(), ws + L.inst[k].hist,
+                              sizeof(double) * rec_len * slot, hipMemcpyDeviceToHost, stream),
+               "hipMemcpyAsync(history)");
+    }
+    HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    for (int k = 0; k < n; ++k) {
+      if (!rho_outs[k]) continue;
+      const int N = hs[k]->N;
+      const size_t rec_len = static_cast<size_t>(N) * N + kScalars;
+      for (int s = 0; s < slot; ++s) {
+        const double *src = host_ring[k].data() + rec_len * s;
+        for (size_t q = 0; q < rec_len - 1; ++q)
+          if (!std::isfinite(src[q]))
+            return fail(HEOM_E_NUMERIC, "non-finite reduced density matrix at record " +
+                                            std::to_string(rec_done + s));
+        unpack_hermitian(N, src, rho_outs[k] + 2 * static_cast<size_t>(N) * N * (rec_done + s));
+      }
+    }
+    rec_done += slot;
+    slot = 0;
+    return HEOM_OK;
+  };
+
+  if (want_rho) {
+    HEOM_HIP(launch_snapshot(mixed, d_descs, n, slot, stream), "snapshot kernel");
+    ++slot;
+  }
+  const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
+  for (int64_t step = 1; step <= n_steps; ++step) {
+    const bool rec = want_rho && (step % record_every == 0);
+    for (int s = 0; s < 4; ++s) {
+      const int hslot = (s == 3 && rec) ? slot : -1;
+      for (const Group &g : groups) {
+        HEOM_HIP(launch_stage(g.fixed, mixed, g.N, g.KP, d_descs, d_work + g.item_begin,
+                              static_cast<int>(g.n_items), block, s, coef[s], hslot, stream),
+                 "stage kernel");
+      }
+    }
+    if (rec) {
+      ++slot;
+      if (slot == kRingRecords) {
+        int rc = drain();
+        if (rc) return rc;
+      }
+    }
+  }
+  if (want_rho) {
+    int rc = drain();
+    if (rc) return rc;
+  }
+  // Final sink populations.
+  std::vector<double> sc(static_cast<size_t>(kScalars) * n);
+  bool want_sinks = false;
+  for (int k = 0; sinks_outs && k < n; ++k) want_sinks = want_sinks || sinks_outs[k] != nullptr;
+  if (want_sinks)
+    for (int k = 0; k < n; ++k)
+      if (sinks_outs[k])
+        HEOM_HIP(hipMemcpyAsync(sc.data() + kScalars * k, ws + L.inst[k].sc_y,
+                                sizeof(double) * kScalars, hipMemcpyDeviceToHost, stream),
+                 "hipMemcpyAsync(scalars)");
+  HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (want_sinks)
+    for (int k = 0; k < n; ++k)
+      if (sinks_outs[k])
+        for (int q = 0; q < 3; ++q) sinks_outs[k][q] = sc[kScalars * k + q];
+  return HEOM_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+
+}  // namespace heom
+
+using namespace heom;
+
+extern "C" {
+
+const char *heom_status_string(int status) {
+  switch (status) {
+    case HEOM_OK: return "ok";
+    case HEOM_E_INVALID: return "invalid argument";
+    case HEOM_E_NOMEM: return "out of memory";
+    case HEOM_E_DEVICE: return "device error";
+    case HEOM_E_NUMERIC: return "numerical failure";
+    case HEOM_E_WORKSPACE: return "workspace error";
+    case HEOM_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char *heom_last_error(void) { return g_last_error.c_str(); }
+
+int heom_build_hierarchy(const heom_system *sys, int32_t depth, heom_hierarchy **out) {
+  if (!out) return fail(HEOM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  heom_hierarchy *h = new (std::nothrow) heom_hierarchy();
+  if (!h) return fail(HEOM_E_NOMEM, "host allocation failed");
+  try {
+    int rc = build_params(sys, h);
+    if (rc == HEOM_OK) {
+      h->depth = depth;
+      rc = build_tables(h);
+    }
+    if (rc != HEOM_OK) {
+      delete h;
+      return rc;
+    }
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    delete h;
+    return fail(HEOM_E_INVALID, "unexpected failure while building the hierarchy");
+  }
+  g_last_error.clear();
+  *out = h;
+  return HEOM_OK;
+}
+
+int heom_hierarchy_info(const heom_hierarchy *h, int64_t *n_ados, int32_t *n_modes,
+                        size_t *workspace_bytes_fp64, size_t *workspace_bytes_fp32) {
+  if (!h) return fail(HEOM_E_INVALID, "hierarchy is NULL");
+  heom_hierarchy *hh = const_cast<heom_hierarchy *>(h);
+  if (n_ados) *n_ados = h->n_ados;
+  if (n_modes) *n_modes = h->M;
+  if (workspace_bytes_fp64) *workspace_bytes_fp64 = make_layout(&hh, 1, HEOM_FP64).total;
+  if (workspace_bytes_fp32) *workspace_bytes_fp32 = make_layout(&hh, 1, HEOM_FP32_MIXED).total;
+  return HEOM_OK;
+}
+
+int heom_hierarchy_tables(const heom_hierarchy *h, int32_t *multi, int32_t *up, int32_t *down) {
+  if (!h) return fail(HEOM_E_INVALID, "hierarchy is NULL");
+  const int M = h->M;
+  if (multi) std::memcpy(multi, h->multi.data(), sizeof(int32_t) * h->multi.size());
+  for (int64_t i = 0; i < h->n_ados; ++i)
+    for (int m = 0; m < M; ++m) {
+      if (up) up[i * M + m] = h->up[static_cast<size_t>(m) * h->stride + i];
+      if (down) down[i * M + m] = h->down[static_cast<size_t>(m) * h->stride + i];
+    }
+  return HEOM_OK;
+}
+
+int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, double *c_im,
+                         double *nu, double *delta) {
+  if (!h) return fail(HEOM_E_INVALID, "hierarchy is NULL");
+  for (int m = 0; m < h->M; ++m) {
+    if (site) site[m] = h->site[m];
+    if (c_re) c_re[m] = h->c_re[m];
+    if (c_im) c_im[m] = h->c_im[m];
+    if (nu) nu[m] = h->nu[m];
+  }
+  if (delta)
+    for (int a = 0; a < h->N; ++a) delta[a] = h->delta[a];
+  return HEOM_OK;
+}
+
+int heom_batch_workspace_bytes(heom_hierarchy *const *hs, int32_t n, int precision, size_t *bytes) {
+  if (!hs || n < 1 || !bytes) return fail(HEOM_E_INVALID, "bad arguments");
+  for (int k = 0; k < n; ++k)
+    if (!hs[k]) return fail(HEOM_E_INVALID, "NULL hierarchy handle");
+  if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
+    return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
+  *bytes = make_layout(hs, n, precision).total;
+  return HEOM_OK;
+}
+
+int heom_propagate(heom_hierarchy *h, int precision, int flags, const double *rho0, double dt_fs,
+                   int64_t n_steps, int64_t record_every, void *d_workspace,
+                   size_t workspace_bytes, void *hip_stream, double *rho_out, double *sinks_out) {
+  try {
+    return propagate_impl(&h, 1, precision, flags, &rho0, dt_fs, n_steps, record_every,
+                          d_workspace, workspace_bytes, hip_stream, &rho_out, &sinks_out);
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+}
+
+int heom_propagate_batch(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
+                         const double *const *rho0s, double dt_fs, int64_t n_steps,
+                         int64_t record_every, void *d_workspace, size_t workspace_bytes,
+                         void *hip_stream, double *const *rho_outs, double *const *sinks_outs) {
+  try {
+    std::vector<double *> ro(n > 0 ? n : 0, nullptr), so(n > 0 ? n : 0, nullptr);
+    for (int k = 0; k < n; ++k) {
+      if (rho_outs) ro[k] = rho_outs[k];
+      if (sinks_outs) so[k] = sinks_outs[k];
+    }
+    return propagate_impl(hs, n, precision, flags, rho0s, dt_fs, n_steps, record_every,
+                          d_workspace, workspace_bytes, hip_stream, ro.data(), so.data());
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+}
+
+int heom_efficiency(heom_hierarchy *h, int precision, const double *rho0, double dt_fs,
+                    double t_end_fs, double pop_tol, void *d_workspace, size_t workspace_bytes,
+                    void *hip_stream, heom_eff_result *out) {
+  if (!h || !out) return fail(HEOM_E_INVALID, "hierarchy or out is NULL");
+  if (!(dt_fs > 0.0)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
+  if (!std::isfinite(t_end_fs)) return fail(HEOM_E_INVALID, "t_end_fs must be finite");
+  if (t_end_fs <= 0.0 && !(pop_tol > 0.0 && pop_tol < 1.0))
+    return fail(HEOM_E_INVALID, "pop_tol must be in (0, 1) when t_end_fs <= 0");
+  const int N = h->N;
+  std::vector<double> rho(2 * static_cast<size_t>(N) * N * 2);
+  double sinks[3] = {0, 0, 0};
+  int64_t steps_done = 0;
+  try {
+    if (t_end_fs > 0.0) {
+      const int64_t steps = static_cast<int64_t>(std::llround(t_end_fs / dt_fs));
+      int rc = heom_propagate(h, precision, 0, rho0, dt_fs, steps, steps > 0 ? steps : 1,
+                              d_workspace, workspace_bytes, hip_stream, rho.data(), sinks);
+      if (rc) return rc;
+      steps_done = steps;
+    } else {
+      const int64_t chunk = 500;
+      const int64_t max_steps = 100000000;
+      int flags = 0;
+      for (;;) {
+        int rc = heom_propagate(h, precision, flags, rho0, dt_fs, chunk, chunk, d_workspace,
+                                workspace_bytes, hip_stream, rho.data(), sinks);
+        if (rc) return rc;
+        flags = HEOM_RESUME;
+        steps_done += chunk;
+        double tr = 0.0;
+        const double *last = rho.data() + 2 * static_cast<size_t>(N) * N;
+        for (int a = 0; a < N; ++a) tr += last[2 * (a * N + a)];
+        if (tr < pop_tol) break;
+        if (steps_done >= max_steps)
+          return fail(HEOM_E_NUMERIC, "population criterion not met within 1e8 steps");
+      }
+    }
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+  const double *last = rho.data() + 2 * static_cast<size_t>(N) * N;
+  double tr = 0.0;
+  for (int a = 0; a < N; ++a) tr += last[2 * (a * N + a)];
+  const double t = steps_done * dt_fs;
+  out->eta = sinks[0];
+  out->p_recomb = sinks[1];
+  out->p_remaining = tr;
+  out->t_end_fs = t;
+  out->mean_trap_time_fs = t * sinks[0] - sinks[2];
+  return HEOM_OK;
+}
+
+int heom_read_state(const heom_hierarchy *h, int precision, const void *d_workspace,
+                    size_t workspace_bytes, void *hip_stream, double *state_out) {
+  if (!h || !state_out) return fail(HEOM_E_INVALID, "hierarchy or state_out is NULL");
+  if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
+    return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
+  heom_hierarchy *hh = const_cast<heom_hierarchy *>(h);
+  const Layout L = make_layout(&hh, 1, precision);
+  if (!d_workspace || workspace_bytes < L.total)
+    return fail(HEOM_E_WORKSPACE, "workspace missing or too small");
+  const char *ws = static_cast<const char *>(d_workspace);
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const int N = h->N;
+  const size_t N2 = static_cast<size_t>(N) * N;
+  const size_t planes = N2 * static_cast<size_t>(h->stride);
+  const bool mixed = precision == HEOM_FP32_MIXED;
+  std::vector<double> p64;
+  std::vector<float> p32;
+  std::vector<double> y0(N2), sc(kScalars);
+  Header cur;
+  try {
+    if (mixed)
+      p32.resize(planes);
+    else
+      p64.resize(planes);
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+  HEOM_HIP(hipMemcpyAsync(&cur, ws + L.header, sizeof(Header), hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync(header)");
+  HEOM_HIP(hipMemcpyAsync(mixed ? static_cast<void *>(p32.data()) : static_cast<void *>(p64.data()),
+                          ws + L.inst[0].y, planes * (mixed ? 4 : 8), hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync(state)");
+  HEOM_HIP(hipMemcpyAsync(y0.data(), ws + L.inst[0].y0, sizeof(double) * N2, hipMemcpyDeviceToHost,
+                          stream),
+           "hipMemcpyAsync(sigma0)");
+  HEOM_HIP(hipMemcpyAsync(sc.data(), ws + L.inst[0].sc_y, sizeof(double) * kScalars,
+                          hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync(scalars)");
+  HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (cur.magic != kMagic || cur.n_inst != 1 || cur.precision != precision ||
+      cur.total_ados != h->n_ados)
+    return fail(HEOM_E_WORKSPACE, "workspace does not hold a run of this hierarchy");
+  std::vector<double> packed(N2);
+  for (int64_t i = 0; i < h->n_ados; ++i) {
+    for (size_t e = 0; e < N2; ++e) {
+      const size_t idx = e * static_cast<size_t>(h->stride) + i;
+      packed[e] = (mixed && i == 0) ? y0[e] : (mixed ? p32[idx] : p64[idx]);
+    }
+    unpack_hermitian(N, packed.data(), state_out + 2 * N2 * i);
+  }
+  double *tail = state_out + 2 * N2 * h->n_ados;
+  tail[0] = sc[0];
+  tail[1] = sc[1];
+  tail[2] = sc[2];
+  return HEOM_OK;
+}
+
+void heom_destroy(heom_hierarchy *h) {
+  if (!h) return;
+  for (auto &t : h->dev) {
+    (void)hipFree(t.up);
+    (void)hipFree(t.down);
+    (void)hipFree(t.occ);
+  }
+  delete h;
+}
+
+}  // extern "C"

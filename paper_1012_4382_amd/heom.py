@@ -1,0 +1,299 @@
+"""Python binding of libheom.so (argument marshalling only).
+
+Every function here forwards to the C-ABI declared in include/heom.h; all of
+the propagation runs in the library's HIP kernels.  PyTorch provides device
+memory (workspaces) and streams.  There is no CPU fallback: if the library is
+missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libheom.so")
+
+HEOM_OK = 0
+HEOM_E_INVALID = -1
+HEOM_E_NOMEM = -2
+HEOM_E_DEVICE = -3
+HEOM_E_NUMERIC = -4
+HEOM_E_WORKSPACE = -5
+HEOM_E_UNSUPPORTED = -6
+
+HEOM_FP64 = 0
+HEOM_FP32_MIXED = 1
+HEOM_RESUME = 1
+HEOM_GENERIC_KERNEL = 2
+
+PRECISIONS = {"fp64": HEOM_FP64, "fp32": HEOM_FP32_MIXED, HEOM_FP64: HEOM_FP64,
+              HEOM_FP32_MIXED: HEOM_FP32_MIXED}
+
+
+class HeomError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+class _System(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32),
+        ("hamiltonian_cm", ctypes.POINTER(ctypes.c_double)),
+        ("lambda_cm", ctypes.POINTER(ctypes.c_double)),
+        ("gamma_inv_fs", ctypes.POINTER(ctypes.c_double)),
+        ("temperature_K", ctypes.c_double),
+        ("n_matsubara", ctypes.c_int32),
+        ("low_temp_correction", ctypes.c_int32),
+        ("theta_form", ctypes.c_int32),
+        ("trap_rate_per_ps", ctypes.POINTER(ctypes.c_double)),
+        ("recomb_rate_per_ps", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class EffResult(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("mean_trap_time_fs", ctypes.c_double),
+                ("p_recomb", ctypes.c_double), ("p_remaining", ctypes.c_double),
+                ("t_end_fs", ctypes.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported function.
+_P = ctypes.POINTER
+_d, _i32, _i64, _sz, _vp = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, \
+    ctypes.c_void_p
+_SIGNATURES = [
+    ("heom_build_hierarchy", ctypes.c_int, [_P(_System), _i32, _P(ctypes.c_void_p)]),
+    ("heom_hierarchy_info", ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_sz), _P(_sz)]),
+    ("heom_hierarchy_tables", ctypes.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32)]),
+    ("heom_hierarchy_modes", ctypes.c_int, [_vp, _P(_i32), _P(_d), _P(_d), _P(_d), _P(_d)]),
+    ("heom_propagate", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _P(_d), _d, _i64, _i64, _vp,
+                                      _sz, _vp, _P(_d), _P(_d)]),
+    ("heom_batch_workspace_bytes", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, _P(_sz)]),
+    ("heom_propagate_batch", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, ctypes.c_int, _P(_P(_d)),
+                                            _d, _i64, _i64, _vp, _sz, _vp, _P(_P(_d)),
+                                            _P(_P(_d))]),
+    ("heom_efficiency", ctypes.c_int, [_vp, ctypes.c_int, _P(_d), _d, _d, _d, _vp, _sz, _vp,
+                                       _P(EffResult)]),
+    ("heom_read_state", ctypes.c_int, [_vp, ctypes.c_int, _vp, _sz, _vp, _P(_d)]),
+    ("heom_destroy", None, [_vp]),
+    ("heom_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("heom_last_error", ctypes.c_char_p, []),
+]
+
+
+def library():
+    """Loads libheom.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1012_4382_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != HEOM_OK:
+        msg = library().heom_last_error().decode()
+        raise HeomError(status, where, msg)
+
+
+def _dp(a):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_double)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+class Hierarchy:
+    """A built hierarchy (owns the C handle).
+
+    ``sys`` keys: H (N x N, cm^-1, real or complex Hermitian), lam (cm^-1, scalar
+    or (N,)), gamma_inv_fs (fs, scalar or (N,)), T (K), K (Matsubara terms),
+    ltc (0/1), theta_form (0/1), trap_per_ps and rec_per_ps ((N,) or None).
+    """
+
+    def __init__(self, sys: dict, depth: int):
+        H = np.ascontiguousarray(np.asarray(sys["H"], np.complex128))
+        N = H.shape[0]
+        self.N = N
+        self.depth = int(depth)
+        keep = {
+            "H": H.view(np.float64).copy(),
+            "lam": np.ascontiguousarray(np.broadcast_to(np.asarray(sys["lam"], float), (N,))),
+            "gi": np.ascontiguousarray(np.broadcast_to(np.asarray(sys["gamma_inv_fs"], float),
+                                                       (N,))),
+            "tr": None if sys.get("trap_per_ps") is None else
+            np.ascontiguousarray(np.asarray(sys["trap_per_ps"], float)),
+            "rc": None if sys.get("rec_per_ps") is None else
+            np.ascontiguousarray(np.asarray(sys["rec_per_ps"], float)),
+        }
+        cs = _System(N, _dp(keep["H"]), _dp(keep["lam"]), _dp(keep["gi"]), float(sys["T"]),
+                     int(sys.get("K", 0)), int(sys.get("ltc", 1)), int(sys.get("theta_form", 0)),
+                     _dp(keep["tr"]), _dp(keep["rc"]))
+        h = ctypes.c_void_p()
+        _check(library().heom_build_hierarchy(ctypes.byref(cs), self.depth, ctypes.byref(h)),
+               "heom_build_hierarchy")
+        self._h = h
+        n, m, b64, b32 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(library().heom_hierarchy_info(h, ctypes.byref(n), ctypes.byref(m),
+                                             ctypes.byref(b64), ctypes.byref(b32)),
+               "heom_hierarchy_info")
+        self.n_ados = n.value
+        self.n_modes = m.value
+        self.workspace_bytes = {HEOM_FP64: b64.value, HEOM_FP32_MIXED: b32.value}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().heom_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tables(self):
+        """(multi [n_ados, M], up [n_ados, M], down [n_ados, M]) in library order."""
+        shape = (self.n_ados, self.n_modes)
+        multi, up, down = (np.zeros(shape, np.int32) for _ in range(3))
+        ip = ctypes.POINTER(ctypes.c_int32)
+        _check(library().heom_hierarchy_tables(self._h, multi.ctypes.data_as(ip),
+                                               up.ctypes.data_as(ip), down.ctypes.data_as(ip)),
+               "heom_hierarchy_tables")
+        return multi, up, down
+
+    def modes(self):
+        """(site, c complex, nu, delta)."""
+        M = self.n_modes
+        site = np.zeros(M, np.int32)
+        cr, ci, nu = np.zeros(M), np.zeros(M), np.zeros(M)
+        delta = np.zeros(self.N)
+        _check(library().heom_hierarchy_modes(
+            self._h, site.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(cr), _dp(ci),
+            _dp(nu), _dp(delta)), "heom_hierarchy_modes")
+        return site, cr + 1j * ci, nu, delta
+
+
+def allocate_workspace(nbytes: int, device=None):
+    """A torch uint8 tensor on the GPU of at least nbytes (256-byte aligned)."""
+    import torch
+
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-t.data_ptr()) % 256
+    return t[off:off + int(nbytes)]
+
+
+def _ws_args(ws):
+    if ws is None:
+        return None, 0
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
+def propagate(h: Hierarchy, rho0, dt_fs: float, n_steps: int, record_every: int = 1,
+              precision="fp64", workspace=None, stream=None, resume: bool = False,
+              generic: bool = False, want_rho: bool = True):
+    """Runs heom_propagate.  Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
+    prec = PRECISIONS[precision]
+    if workspace is None:
+        workspace = allocate_workspace(h.workspace_bytes[prec])
+    ptr, nbytes = _ws_args(workspace)
+    flags = (HEOM_RESUME if resume else 0) | (HEOM_GENERIC_KERNEL if generic else 0)
+    r0 = None
+    if rho0 is not None:
+        r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
+    n_rec = n_steps // record_every + 1
+    rho = np.zeros((n_rec, h.N, h.N), np.complex128) if want_rho else None
+    sinks = np.zeros(3)
+    _check(library().heom_propagate(h.handle, prec, flags, _dp(r0), float(dt_fs), int(n_steps),
+                                    int(record_every), ptr, nbytes, _stream_handle(stream),
+                                    _dp(None if rho is None else rho.view(np.float64)),
+                                    _dp(sinks)), "heom_propagate")
+    return rho, sinks, workspace
+
+
+def batch_workspace_bytes(hs, precision="fp64") -> int:
+    arr = (ctypes.c_void_p * len(hs))(*[h.handle.value for h in hs])
+    out = ctypes.c_size_t()
+    _check(library().heom_batch_workspace_bytes(arr, len(hs), PRECISIONS[precision],
+                                                ctypes.byref(out)), "heom_batch_workspace_bytes")
+    return out.value
+
+
+def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1,
+                    precision="fp64", workspace=None, stream=None, resume: bool = False,
+                    generic: bool = False, want_rho: bool = True):
+    """Runs heom_propagate_batch.  Returns (list of rho | None, sinks [n, 3], workspace)."""
+    n = len(hs)
+    prec = PRECISIONS[precision]
+    if workspace is None:
+        workspace = allocate_workspace(batch_workspace_bytes(hs, precision))
+    ptr, nbytes = _ws_args(workspace)
+    flags = (HEOM_RESUME if resume else 0) | (HEOM_GENERIC_KERNEL if generic else 0)
+    DP = ctypes.POINTER(ctypes.c_double)
+    keep = []
+    r0 = (DP * n)()
+    for k in range(n):
+        if rho0s is not None and rho0s[k] is not None:
+            a = np.ascontiguousarray(np.asarray(rho0s[k], np.complex128)).view(np.float64)
+            keep.append(a)
+            r0[k] = _dp(a)
+    n_rec = n_steps // record_every + 1
+    rhos = [np.zeros((n_rec, h.N, h.N), np.complex128) for h in hs] if want_rho else None
+    sinks = np.zeros((n, 3))
+    ro = (DP * n)()
+    so = (DP * n)()
+    for k in range(n):
+        if rhos is not None:
+            ro[k] = _dp(rhos[k].view(np.float64))
+        so[k] = sinks[k].ctypes.data_as(DP)
+    arr = (ctypes.c_void_p * n)(*[h.handle.value for h in hs])
+    _check(library().heom_propagate_batch(arr, n, prec, flags, r0, float(dt_fs), int(n_steps),
+                                          int(record_every), ptr, nbytes, _stream_handle(stream),
+                                          ro, so), "heom_propagate_batch")
+    return rhos, sinks, workspace
+
+
+def efficiency(h: Hierarchy, rho0, dt_fs: float, t_end_fs: float, pop_tol: float = 1e-5,
+               precision="fp64", workspace=None, stream=None) -> dict:
+    prec = PRECISIONS[precision]
+    if workspace is None:
+        workspace = allocate_workspace(h.workspace_bytes[prec])
+    ptr, nbytes = _ws_args(workspace)
+    r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
+    out = EffResult()
+    _check(library().heom_efficiency(h.handle, prec, _dp(r0), float(dt_fs), float(t_end_fs),
+                                     float(pop_tol), ptr, nbytes, _stream_handle(stream),
+                                     ctypes.byref(out)), "heom_efficiency")
+    return {f: getattr(out, f) for f, _ in EffResult._fields_}
+
+
+def read_state(h: Hierarchy, workspace, precision="fp64", stream=None):
+    """(sigma [n_ados, N, N] complex in library order, scalars [3])."""
+    ptr, nbytes = _ws_args(workspace)
+    buf = np.zeros(2 * h.n_ados * h.N * h.N + 3)
+    _check(library().heom_read_state(h.handle, PRECISIONS[precision], ptr, nbytes,
+                                     _stream_handle(stream), _dp(buf)), "heom_read_state")
+    sig = buf[: 2 * h.n_ados * h.N * h.N].view(np.complex128).reshape(h.n_ados, h.N, h.N)
+    return sig, buf[2 * h.n_ados * h.N * h.N:].copy()

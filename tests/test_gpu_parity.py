@@ -1,0 +1,290 @@
+"""GPU parity: libheom.so (through its C-ABI) against the FP64 oracle.
+
+Each case runs the HIP path and the oracle on the same seeded inputs and
+compares element by element.  FP64 bar: 1e-10 relative (max deviation over the
+whole trajectory divided by the largest entry).  FP32-mixed bar: 1e-5 on
+populations and efficiency.  Full-size workloads, where the oracle would take
+minutes, are compared on their first steps (the same run, sampled) and checked
+for the invariants over the whole run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1012_4382_amd import heom, workloads
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU (run with -m 'not gpu' on CPU)")
+    heom.library()
+    yield
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _state_by_multi(h, sig):
+    multi, _, _ = h.tables()
+    return {tuple(int(v) for v in r): sig[i] for i, r in enumerate(multi)}
+
+
+def _oracle_state_by_multi(sys, depth, sig):
+    multi = oracle.enumerate_ados(sys, depth)
+    return {tuple(int(v) for v in r): sig[i] for i, r in enumerate(multi)}
+
+
+# --- FP64 trajectories ---------------------------------------------------------
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_dimer_full_trajectory_and_state(generic):
+    w = workloads.dimer()
+    _say(f"case: dimer N=2 D=4 1000 steps generic={generic}")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    rho, sinks, ws = heom.propagate(h, w["rho0"], w["dt"], w["steps"], generic=generic)
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], want_state=True)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    # Every ADO, matched by multi-index.
+    sig, sc = heom.read_state(h, ws)
+    got = _state_by_multi(h, sig)
+    want = _oracle_state_by_multi(w["system"], w["depth"], ref["state"][0])
+    assert got.keys() == want.keys()
+    scale = max(np.max(np.abs(v)) for v in want.values())
+    for k in want:
+        assert np.max(np.abs(got[k] - want[k])) <= FP64_TOL * scale, k
+    # Populations and the coherence actually move.
+    assert abs(rho[-1, 0, 0] - 1.0) > 0.05 and abs(rho[-1, 0, 1]) > 1e-3
+
+
+@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("site", [1, 6])
+def test_fmo_like_with_sinks_reduced_depth(generic, site):
+    w = workloads.fmo_like(seed=0, site=site, depth=3, steps=2000)
+    _say(f"case: fmo_like N=7 D=3 site={site} 2000 steps generic={generic}")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=10,
+                                   generic=generic)
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=10)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
+    assert abs(sinks[1] - ref["scalars"][1]) <= FP64_TOL * abs(ref["scalars"][1])
+    assert abs(sinks[2] - ref["scalars"][2]) <= FP64_TOL * abs(ref["scalars"][2])
+    assert sinks[0] > 1e-3
+
+
+def test_fmo_like_full_size_sampled_and_invariants():
+    """Depth 7 (3432 ADOs), the benchmarked shape: first 60 steps against the
+    oracle, then the whole 5000-step run for population conservation."""
+    w = workloads.fmo_like(seed=1, site=1)
+    _say("case: fmo_like N=7 D=7 3432 ADOs, sampled 60 steps + 5000-step invariants")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    assert h.n_ados == 3432
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], 60)
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], 60)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=50)
+    tr = np.trace(rho, axis1=1, axis2=2)
+    assert np.max(np.abs(tr.imag)) < 1e-14
+    # Tr sigma_0 + P_trap + P_rec = 1 holds exactly for RK4; check the end point.
+    assert abs(tr[-1].real + sinks[0] + sinks[1] - 1.0) < 1e-12
+    pops = np.real(np.diagonal(rho, axis1=1, axis2=2))
+    assert np.all(pops > -1e-3) and np.all(pops < 1 + 1e-9)
+    assert 0.05 < sinks[0] < 1.0
+
+
+def test_matsubara_term_sweep_shape():
+    """One Matsubara term per bath (14 modes), depth 3: 680 ADOs, 1000 steps."""
+    w = workloads.sweep_instance(0)
+    w["depth"] = 3
+    _say("case: sweep instance 0, N=7 K=1 D=3 680 ADOs, 1000 steps")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=5)
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=5)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
+
+
+def test_complex_hamiltonian_generic_kernel():
+    rng = np.random.default_rng(5)
+    N = 3
+    A = rng.normal(0, 30, (N, N))
+    H = np.diag([12400.0, 12300.0, 12250.0]) + (A + A.T) / 2 + 1j * (A - A.T) / 2
+    sys = workloads.system(H, lam=np.array([30.0, 60.0, 90.0]),
+                           gamma_inv_fs=np.array([40.0, 80.0, 120.0]), T=150.0, K=2,
+                           trap=np.array([0.0, 0.5, 0.0]), rec=np.full(N, 1e-3))
+    rho0 = np.array([[0.6, 0.2 + 0.1j, 0], [0.2 - 0.1j, 0.4, 0], [0, 0, 0]])
+    _say("case: complex H N=3 K=2 D=3, generic kernel")
+    h = heom.Hierarchy(sys, 3)
+    rho, sinks, _ = heom.propagate(h, rho0, 0.5, 800, record_every=4)
+    ref = oracle.propagate(sys, 3, rho0, 0.5, 800, record_every=4)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
+
+
+@pytest.mark.parametrize("N,depth,steps", [(12, 2, 400), (24, 1, 300), (9, 2, 300)])
+def test_generic_kernel_larger_sites(N, depth, steps):
+    """Chains of the serving workload's sizes through the generic kernel."""
+    rng = np.random.default_rng(N)
+    H = np.diag(rng.normal(12400, 100, N))
+    for i in range(N - 1):
+        H[i, i + 1] = H[i + 1, i] = rng.normal(-80, 20)
+    trap = np.zeros(N)
+    trap[-1] = 1.0
+    sys = workloads.system(H, trap=trap, rec=np.full(N, 1e-3))
+    rho0 = workloads.site_state(N, 1)
+    _say(f"case: chain N={N} D={depth} {steps} steps")
+    h = heom.Hierarchy(sys, depth)
+    rho, sinks, _ = heom.propagate(h, rho0, 1.0, steps, record_every=10)
+    ref = oracle.propagate(sys, depth, rho0, 1.0, steps, record_every=10)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+
+
+# --- FP32 mixed precision ----------------------------------------------------------
+
+@pytest.mark.parametrize("T", [77.0, 300.0])
+def test_fp32_mixed_against_fp64_oracle(T):
+    w = workloads.fmo_like(seed=0, site=1, depth=4, T=T, steps=3000)
+    _say(f"case: fp32-mixed fmo_like N=7 D=4 T={T} 3000 steps")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=10,
+                                   precision="fp32")
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=10)
+    p = np.real(np.diagonal(rho, axis1=1, axis2=2))
+    pr = np.real(np.diagonal(ref["rho"], axis1=1, axis2=2))
+    err_pop = np.max(np.abs(p - pr))
+    err_eta = abs(sinks[0] - ref["scalars"][0])
+    _say(f"  max |dp| = {err_pop:.3e}, |d eta| = {err_eta:.3e}")
+    assert err_pop <= FP32_TOL
+    assert err_eta <= FP32_TOL * max(1.0, ref["scalars"][0])
+
+
+def test_fp32_mixed_full_size_sampled():
+    """Precision workload shape (depth 8, 6435 ADOs): first 100 steps vs oracle."""
+    w = workloads.fmo_like(seed=1, site=1, depth=8, T=77.0, steps=100)
+    _say("case: fp32-mixed fmo_like N=7 D=8 6435 ADOs, 100 steps")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    assert h.n_ados == 6435
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], precision="fp32")
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"])
+    assert np.max(np.abs(rho - ref["rho"])) <= FP32_TOL
+
+
+# --- batching, resume, determinism ---------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_equals_single_solves(precision):
+    ws_ = [workloads.fmo_like(seed=s, site=site, depth=4, steps=300) for s in (0, 1) for site in (1, 6)]
+    ws_.append(workloads.sweep_instance(3))
+    ws_[-1]["depth"], ws_[-1]["steps"] = 2, 300
+    ws_.append(workloads.dimer())
+    ws_[-1]["steps"] = 300
+    _say(f"case: batch of {len(ws_)} mixed instances vs single solves ({precision})")
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in ws_]
+    rhos, sinks, _ = heom.propagate_batch(hs, [w["rho0"] for w in ws_], 1.0, 300, record_every=3,
+                                          precision=precision)
+    for k, (h, w) in enumerate(zip(hs, ws_)):
+        r1, s1, _ = heom.propagate(h, w["rho0"], 1.0, 300, record_every=3, precision=precision)
+        assert np.array_equal(rhos[k], r1), k
+        assert np.array_equal(sinks[k], s1), k
+
+
+def test_resume_is_bitwise_identical():
+    w = workloads.fmo_like(seed=2, site=6, depth=4, steps=300)
+    _say("case: resume 100 + 200 vs 300 steps")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    r_full, s_full, _ = heom.propagate(h, w["rho0"], 1.0, 300, record_every=100)
+    r_a, _, ws = heom.propagate(h, w["rho0"], 1.0, 100, record_every=100)
+    r_b, s_b, _ = heom.propagate(h, None, 1.0, 200, record_every=100, workspace=ws, resume=True)
+    assert np.array_equal(r_full[1], r_a[1])
+    assert np.array_equal(r_full[2:], r_b[1:])
+    assert np.array_equal(s_full, s_b)
+
+
+def test_runs_are_deterministic():
+    w = workloads.fmo_like(seed=3, site=1, depth=5, steps=200)
+    _say("case: determinism, two identical runs")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    a = heom.propagate(h, w["rho0"], 1.0, 200)
+    b = heom.propagate(h, w["rho0"], 1.0, 200)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# --- efficiency entry point and edge cases ------------------------------------------------
+
+def test_efficiency_fixed_horizon_and_criterion():
+    w = workloads.fmo_like(seed=0, site=1, depth=2)
+    _say("case: heom_efficiency fixed horizon 2 ps and t_max criterion")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    out = heom.efficiency(h, w["rho0"], 1.0, 2000.0)
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], 1.0, 2000, record_every=2000)
+    eta, q = ref["scalars"][0], ref["scalars"][2]
+    assert abs(out["eta"] - eta) <= FP64_TOL * eta
+    assert abs(out["mean_trap_time_fs"] - (2000.0 * eta - q)) <= 1e-9 * (2000.0 * eta - q)
+    assert abs(out["p_remaining"] - np.trace(ref["rho"][-1]).real) <= 1e-12
+    assert out["t_end_fs"] == 2000.0
+    # Run to the population criterion with fast sinks (trap 20/ps on all sites).
+    sysf = dict(w["system"], trap_per_ps=np.full(7, 20.0))
+    hf = heom.Hierarchy(sysf, 2)
+    crit = heom.efficiency(hf, w["rho0"], 1.0, 0.0, pop_tol=1e-5)
+    assert crit["p_remaining"] < 1e-5
+    assert abs(crit["eta"] + crit["p_recomb"] + crit["p_remaining"] - 1.0) < 1e-12
+
+
+def test_edge_cases():
+    _say("case: edge cases (depth 0, one site, zero steps, ragged record_every)")
+    # Depth 0: sigma_0 alone (Liouvillian, sinks, correction residual).
+    w = workloads.fmo_like(seed=0, site=1, depth=0, steps=100)
+    h = heom.Hierarchy(w["system"], 0)
+    assert h.n_ados == 1
+    rho, s, _ = heom.propagate(h, w["rho0"], 1.0, 100, record_every=7)
+    ref = oracle.propagate(w["system"], 0, w["rho0"], 1.0, 100, record_every=7)
+    assert rho.shape[0] == 100 // 7 + 1
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    # One site: only damping and sinks act on populations.
+    sys1 = workloads.system(np.array([[12400.0]]), trap=np.array([2.0]), rec=np.array([0.5]))
+    h1 = heom.Hierarchy(sys1, 3)
+    rho, s, _ = heom.propagate(h1, np.array([[1.0]]), 0.5, 400)
+    ref = oracle.propagate(sys1, 3, np.array([[1.0]]), 0.5, 400)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    assert abs(s[0] - ref["scalars"][0]) <= FP64_TOL * ref["scalars"][0]
+    # Zero steps returns the initial state only.
+    rho, s, _ = heom.propagate(h1, np.array([[1.0]]), 0.5, 0)
+    assert rho.shape == (1, 1, 1) and rho[0, 0, 0] == 1.0 and np.all(s == 0)
+    # A coherent initial state (off-diagonal entries set).
+    w = workloads.dimer()
+    r0 = np.array([[0.5, 0.3 - 0.2j], [0.3 + 0.2j, 0.5]])
+    h = heom.Hierarchy(w["system"], 6)
+    rho, _, _ = heom.propagate(h, r0, 1.0, 500, record_every=5)
+    ref = oracle.propagate(w["system"], 6, r0, 1.0, 500, record_every=5)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    # A record count that exceeds the device ring (512) is drained in chunks.
+    rho, _, _ = heom.propagate(h, r0, 1.0, 1100)
+    ref = oracle.propagate(w["system"], 6, r0, 1.0, 1100)
+    assert _rel(rho, ref["rho"]) <= FP64_TOL
+
+
+def test_numeric_failure_is_reported():
+    """A step far beyond RK4's stability region blows up: HEOM_E_NUMERIC."""
+    w = workloads.dimer()
+    _say("case: unstable dt reports HEOM_E_NUMERIC")
+    h = heom.Hierarchy(w["system"], 4)
+    with pytest.raises(heom.HeomError) as ei:
+        heom.propagate(h, w["rho0"], 400.0, 2000, record_every=100)
+    assert ei.value.status == heom.HEOM_E_NUMERIC
