@@ -32,6 +32,8 @@ def _parse():
     p.add_argument("--rk4-steps", type=int, default=5000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--kernel", default="auto", choices=["auto", "lane", "generic"],
+                   help="stage kernel (lane and generic are diagnostic)")
     return p.parse_args()
 
 
@@ -81,7 +83,8 @@ def main():
 
     def one_pass(precision="fp64", workspace=ws, hh=hs, r0=rho0s):
         return heom.propagate_batch(hh, r0, 1.0, steps_rk, record_every=record_every,
-                                    precision=precision, workspace=workspace, stream=stream)
+                                    precision=precision, workspace=workspace, stream=stream,
+                                    kernel=args.kernel)
 
     for _ in range(args.warmup):
         one_pass()
@@ -102,10 +105,10 @@ def main():
     n_launch_steps = 500
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     heom.propagate_batch(hs, rho0s, 1.0, 20, record_every=20, workspace=ws, stream=stream,
-                         want_rho=False)
+                         want_rho=False, kernel=args.kernel)
     ev0.record(stream)
     heom.propagate_batch(hs, rho0s, 1.0, n_launch_steps, record_every=n_launch_steps,
-                         workspace=ws, stream=stream, want_rho=False)
+                         workspace=ws, stream=stream, want_rho=False, kernel=args.kernel)
     ev1.record(stream)
     ev1.synchronize()
     kernel_ms = ev0.elapsed_time(ev1) / (4 * n_launch_steps)
@@ -133,7 +136,9 @@ def main():
                    "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"stage_fixed<{N},1,double>",
+                     "kernel": {"auto": f"stage_tile<{N},1,double>",
+                                "lane": f"stage_fixed<{N},1,double>",
+                                "generic": "stage_generic<double>"}[args.kernel],
                      "kernel_avg_us": kernel_ms * 1e3, "bytes_per_launch": bytes_per_launch},
         "population_defect": defect,
     }

@@ -57,8 +57,10 @@ enum { HEOM_FP64 = 0, HEOM_FP32_MIXED = 1 };
 /* Flags for heom_propagate / heom_propagate_batch. */
 enum {
   HEOM_RESUME = 1,          /* continue from the state held in the workspace   */
-  HEOM_GENERIC_KERNEL = 2   /* diagnostic: use the generic stage kernel even
+  HEOM_GENERIC_KERNEL = 2,  /* diagnostic: use the generic stage kernel even
                                where a specialised one exists                   */
+  HEOM_LANE_KERNEL = 4      /* diagnostic: use the one-lane-per-ADO specialised
+                               kernel instead of the LDS-tiled one (N <= 8)     */
 };
 
 typedef struct heom_hierarchy heom_hierarchy; /* opaque, library-owned */

@@ -81,6 +81,13 @@ struct InstDesc {
   int32_t N, M, KP, pad_;
 };
 
+// Stage kernel variants.
+//  kTile:    N <= 8, real H; 64 ADOs per workgroup staged in LDS, one packed
+//            element per wave (default where available)
+//  kLane:    N <= 8, real H; one lane per ADO, ADO held in registers
+//  kGeneric: any N, complex H; one lane per ADO, reads from the planes
+enum class KernelKind { kTile, kLane, kGeneric };
+
 // A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
 struct WorkItem {
   int32_t inst;

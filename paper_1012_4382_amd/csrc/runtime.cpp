@@ -24,7 +24,8 @@ namespace heom {
 
 // stage_kernels.hip
 bool has_fixed_kernel(int N, int KP);
-hipError_t launch_stage(bool fixed, bool mixed, int N, int KP, const InstDesc *descs,
+int tile_threads(int N);
+hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
                         const WorkItem *work, int n_items, int block, int stage, double coef,
                         int hist_slot, hipStream_t stream);
 hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
@@ -51,7 +52,7 @@ int dev_fail(hipError_t e, const char *what) {
     if (e_ != hipSuccess) return dev_fail(e_, what); \
   } while (0)
 
-// ADOs handled by one workgroup (one lane per ADO).
+// ADOs handled by one workgroup of the lane-per-ADO kernels.
 int block_ados() {
   static int v = [] {
     const char *s = std::getenv("HEOM_BLOCK_ADOS");
@@ -201,8 +202,9 @@ void unpack_hermitian(int N, const double *packed, double *rho) {
 }
 
 struct Group {
-  bool fixed;
+  KernelKind kind;
   int N, KP;
+  int ados_per_item, threads;
   int64_t item_begin, n_items;
 };
 
@@ -215,7 +217,10 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
     if (!hs[k]) return fail(HEOM_E_INVALID, "NULL hierarchy handle");
   if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
     return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
-  if (flags & ~(HEOM_RESUME | HEOM_GENERIC_KERNEL)) return fail(HEOM_E_INVALID, "unknown flags");
+  if (flags & ~(HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL))
+    return fail(HEOM_E_INVALID, "unknown flags");
+  if ((flags & HEOM_GENERIC_KERNEL) && (flags & HEOM_LANE_KERNEL))
+    return fail(HEOM_E_INVALID, "HEOM_GENERIC_KERNEL and HEOM_LANE_KERNEL are exclusive");
   if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
   if (n_steps < 0) return fail(HEOM_E_INVALID, "n_steps must be >= 0");
   if (record_every < 1) return fail(HEOM_E_INVALID, "record_every must be >= 1");
@@ -274,24 +279,32 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
     d.KP = hs[k]->KP;
     d.pad_ = 0;
   }
-  const bool allow_fixed = (flags & HEOM_GENERIC_KERNEL) == 0;
-  const int block = block_ados();
-  std::map<std::tuple<bool, int, int>, std::vector<int>> by_key;
+  std::map<std::tuple<int, int, int>, std::vector<int>> by_key;
   for (int k = 0; k < n; ++k) {
     const heom_hierarchy *h = hs[k];
-    const bool fixed = allow_fixed && h->h_real && has_fixed_kernel(h->N, h->KP);
-    by_key[std::make_tuple(fixed, h->N, fixed ? h->KP : 0)].push_back(k);
+    KernelKind kind = KernelKind::kGeneric;
+    if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real && has_fixed_kernel(h->N, h->KP))
+      kind = (flags & HEOM_LANE_KERNEL) ? KernelKind::kLane : KernelKind::kTile;
+    const int kp = (kind == KernelKind::kGeneric) ? 0 : h->KP;
+    by_key[std::make_tuple(static_cast<int>(kind), h->N, kp)].push_back(k);
   }
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   for (const auto &kv : by_key) {
     Group g;
-    g.fixed = std::get<0>(kv.first);
+    g.kind = static_cast<KernelKind>(std::get<0>(kv.first));
     g.N = std::get<1>(kv.first);
-    g.KP = g.fixed ? std::get<2>(kv.first) : 0;
+    g.KP = std::get<2>(kv.first);
+    if (g.kind == KernelKind::kTile) {
+      g.ados_per_item = 64;
+      g.threads = tile_threads(g.N);
+    } else {
+      g.ados_per_item = block_ados();
+      g.threads = g.ados_per_item;
+    }
     g.item_begin = static_cast<int64_t>(items.size());
     for (int k : kv.second)
-      for (int64_t first = 0; first < hs[k]->n_ados; first += block)
+      for (int64_t first = 0; first < hs[k]->n_ados; first += g.ados_per_item)
         items.push_back({k, static_cast<int32_t>(first)});
     g.n_items = static_cast<int64_t>(items.size()) - g.item_begin;
     groups.push_back(g);
@@ -323,8 +336,10 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
   const InstDesc *d_descs = reinterpret_cast<const InstDesc *>(ws + L.descs);
   const WorkItem *d_work = reinterpret_cast<const WorkItem *>(ws + L.work);
   if (!resume) {
-    HEOM_HIP(launch_init(mixed, d_descs, d_work, static_cast<int>(items.size()), block, stream),
-             "init kernel");
+    for (const Group &g : groups)
+      HEOM_HIP(launch_init(mixed, d_descs, d_work + g.item_begin, static_cast<int>(g.n_items),
+                           g.ados_per_item, stream),
+               "init kernel");
     HEOM_HIP(hipMemcpyAsync(ws + L.header, &hdr, sizeof(Header), hipMemcpyHostToDevice, stream),
              "hipMemcpyAsync(header)");
   }
@@ -371,14 +386,14 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
   for (int64_t step = 1; step <= n_steps; ++step) {
     const bool rec = want_rho && (step % record_every == 0);
     for (int s = 0; s < 4; ++s) {
-      const int hslot = (s == 3 && rec) ? slot : -1;
       for (const Group &g : groups) {
-        HEOM_HIP(launch_stage(g.fixed, mixed, g.N, g.KP, d_descs, d_work + g.item_begin,
-                              static_cast<int>(g.n_items), block, s, coef[s], hslot, stream),
+        HEOM_HIP(launch_stage(g.kind, mixed, g.N, g.KP, d_descs, d_work + g.item_begin,
+                              static_cast<int>(g.n_items), g.threads, s, coef[s], -1, stream),
                  "stage kernel");
       }
     }
     if (rec) {
+      HEOM_HIP(launch_snapshot(mixed, d_descs, n, slot, stream), "snapshot kernel");
       ++slot;
       if (slot == kRingRecords) {
         int rc = drain();

@@ -43,6 +43,8 @@
 //    straight from the planes (all such reads are coalesced across lanes).
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "heom_internal.h"
 
 namespace heom {
@@ -52,6 +54,36 @@ template <typename C>
 struct Cx {
   C re, im;
 };
+
+// Address-space views of workspace pointers.  Pointers read from the
+// descriptor are generic; without these casts every access would be a FLAT
+// instruction (counted against both the vector-memory and the LDS counters, so
+// each LDS wait would also wait for every outstanding global load) and the
+// wave-uniform parameter reads could not become scalar loads.
+#define HEOM_GLOBAL __attribute__((address_space(1)))
+#define HEOM_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const HEOM_GLOBAL T *gmem(const T *p) {
+  return (const HEOM_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ HEOM_GLOBAL T *gmem(T *p) {
+  return (HEOM_GLOBAL T *)p;
+}
+__device__ __forceinline__ const HEOM_CONST double *cmem(const double *p) {
+  return (const HEOM_CONST double *)p;
+}
+// Load / store at a 32-bit per-lane byte offset from a wave-uniform base, so
+// that the address is one VGPR added to a scalar base (no 64-bit arithmetic
+// per lane).  Every plane, table and state buffer is far below 4 GiB.
+template <typename T>
+__device__ __forceinline__ T ld_off(const HEOM_GLOBAL T *base, uint32_t off) {
+  return *(const HEOM_GLOBAL T *)((const HEOM_GLOBAL char *)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(HEOM_GLOBAL T *base, uint32_t off, T v) {
+  *(HEOM_GLOBAL T *)((HEOM_GLOBAL char *)base + off) = v;
+}
 
 // Buffers used by stage s.
 struct StageBufs {
@@ -457,6 +489,364 @@ __global__ void __launch_bounds__(256) stage_generic(const InstDesc *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Tile kernel: compile-time N <= 8 and modes per site, real Hamiltonian.
+// A workgroup stages the stage input of 64 consecutive ADOs (one "tile") and
+// their neighbour tables in LDS; wave w then produces the packed elements
+// p = w, w + W, w + 2W, ... for all 64 ADOs.  Each wave's element group is
+// known at compile time (the kernel dispatches on the wave index), so every
+// LDS offset, Hamiltonian entry and plane index is a constant: a wave issues
+// all LDS reads and neighbour gathers of its elements back to back and pays
+// the memory latency about once.  The ADOs of a tile are consecutive, so each
+// gather of a wave reads one element plane at nearly consecutive indices.
+// ---------------------------------------------------------------------------
+
+constexpr int kTile = 64;
+
+// Minimum waves per SIMD requested from the register allocator for the tile
+// kernel (trades registers for resident waves).
+#ifndef HEOM_TILE_MIN_WAVES_PER_SIMD
+#define HEOM_TILE_MIN_WAVES_PER_SIMD 1
+#endif
+
+// Packed element p -> (a, b), a <= b: p < N are the diagonal entries, then
+// the pairs a < b in row-major order.
+__host__ __device__ constexpr int elem_a(int N, int p) {
+  if (p < N) return p;
+  int q = p - N, a = 0;
+  while (q >= N - 1 - a) {
+    q -= N - 1 - a;
+    ++a;
+  }
+  return a;
+}
+__host__ __device__ constexpr int elem_b(int N, int p) {
+  if (p < N) return p;
+  int q = p - N, a = 0;
+  while (q >= N - 1 - a) {
+    q -= N - 1 - a;
+    ++a;
+  }
+  return a + 1 + q;
+}
+// Plane of the real part of entry (r, c) and of its imaginary part (N*N, a
+// plane of zeros, on the diagonal), and the sign of the imaginary part.
+__host__ __device__ constexpr int ent_re(int N, int r, int c) {
+  return r == c ? r : (r < c ? re_plane(N, r, c) : re_plane(N, c, r));
+}
+__host__ __device__ constexpr int ent_im(int N, int r, int c) {
+  return r == c ? N * N : ent_re(N, r, c) + 1;
+}
+__host__ __device__ constexpr int ent_sg(int r, int c) { return r > c ? -1 : 1; }
+
+// Target packed elements per wave of the tile kernel, and how many of a
+// wave's elements have their global loads in flight together (one chunk).
+#ifndef HEOM_TILE_ELEMS_PER_WAVE
+#define HEOM_TILE_ELEMS_PER_WAVE 4
+#endif
+#ifndef HEOM_TILE_CHUNK
+#define HEOM_TILE_CHUNK 4
+#endif
+
+// Waves per tile workgroup: the divisor of the N(N+1)/2 packed elements
+// (at most 16) that gives closest to HEOM_TILE_ELEMS_PER_WAVE elements per wave.
+__host__ __device__ constexpr int tile_waves_for(int N) {
+  const int P = N * (N + 1) / 2;
+  const int t = HEOM_TILE_ELEMS_PER_WAVE;
+  int best = 1;
+  for (int w = 1; w <= 16 && w <= P; ++w) {
+    if (P % w) continue;
+    const int d_best = (t * best - P) < 0 ? P - t * best : t * best - P;
+    const int d_w = (t * w - P) < 0 ? P - t * w : t * w - P;
+    if (d_w < d_best) best = w;
+  }
+  return best;
+}
+
+template <typename T>
+struct TileCtx {
+  const HEOM_CONST double *P;         // parameter block
+  const T *sx;                        // LDS tile of the stage input, [N*N + 1][64]
+  const int32_t *sup, *sdn;
+  const uint8_t *socc;                // LDS neighbour tables, [M][64]
+  const HEOM_GLOBAL T *X;             // stage input planes (neighbour gathers)
+  const HEOM_GLOBAL T *Yp;            // state planes
+  HEOM_GLOBAL T *Out;                 // output planes
+  const HEOM_GLOBAL double *x0, *y0;  // FP64 sigma_0 (mixed precision)
+  HEOM_GLOBAL double *out0;
+  int64_t S, i;
+  int lane;
+  double damp, coef;
+};
+
+// Values of one element (A, B) read from global memory: the same element of
+// the deeper (y*) and shallower (z*) neighbours along the modes of sites A
+// and B, and of the state.
+template <typename C, int KP>
+struct ElemLoads {
+  C yar[KP], yai[KP], ybr[KP], ybi[KP];  // deeper neighbours
+  C zar[KP], zai[KP], zbr[KP], zbi[KP];  // shallower neighbours
+  C str, sti;                            // state
+};
+
+// Phase 1 of element (A, B): issue every global load.  Neighbour gathers are
+// branch-free: a missing neighbour (index -1) reads the lane's own entry and
+// is weighted by zero (the occupation is zero exactly where the shallower
+// neighbour is missing), so the loads of all elements of a wave are in
+// flight together.  X0SRC reads the state from the FP64 copy of sigma_0.
+template <int N, int KP, int A, int B, typename C, typename T, bool X0SRC>
+__device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> &L) {
+  constexpr int E = ent_re(N, A, B);
+  const int lane = c.lane;
+  const HEOM_GLOBAL T *pre = c.X + E * c.S;         // wave-uniform plane bases
+  const HEOM_GLOBAL T *pim = c.X + (E + 1) * c.S;
+  const uint32_t self = static_cast<uint32_t>(c.i);
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int ma = A * KP + k;
+    const int mb = B * KP + k;
+    if constexpr (A != B) {
+      const int ja = c.sup[ma * kTile + lane];
+      const int jb = c.sup[mb * kTile + lane];
+      const uint32_t oa = (ja >= 0 ? static_cast<uint32_t>(ja) : self) * sizeof(T);
+      const uint32_t ob = (jb >= 0 ? static_cast<uint32_t>(jb) : self) * sizeof(T);
+      L.yar[k] = static_cast<C>(ld_off(pre, oa));
+      L.yai[k] = static_cast<C>(ld_off(pim, oa));
+      L.ybr[k] = static_cast<C>(ld_off(pre, ob));
+      L.ybi[k] = static_cast<C>(ld_off(pim, ob));
+    }
+    const int ja = c.sdn[ma * kTile + lane];
+    const int jb = c.sdn[mb * kTile + lane];
+    const uint32_t oa = (ja >= 0 ? static_cast<uint32_t>(ja) : self) * sizeof(T);
+    const uint32_t ob = (jb >= 0 ? static_cast<uint32_t>(jb) : self) * sizeof(T);
+    L.zar[k] = static_cast<C>(ld_off(pre, oa));
+    L.zbr[k] = static_cast<C>(ld_off(pre, ob));
+    if constexpr (A != B) {
+      L.zai[k] = static_cast<C>(ld_off(pim, oa));
+      L.zbi[k] = static_cast<C>(ld_off(pim, ob));
+    }
+  }
+  if constexpr (X0SRC) {
+    L.str = static_cast<C>(c.y0[E]);
+    if constexpr (A != B) L.sti = static_cast<C>(c.y0[E + 1]);
+  } else {
+    const uint32_t oi = self * sizeof(T);
+    L.str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
+    if constexpr (A != B) L.sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
+  }
+}
+
+// Phase 2 of element (A, B): right-hand side from the LDS tile and the loaded
+// values, RK4 stage update, store.  C is the arithmetic type.
+template <int N, int KP, int A, int B, typename C, typename T, bool X0SRC>
+__device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads<C, KP> &L) {
+  constexpr int M = N * KP;
+  constexpr int o_hg = 2 * N * N, o_dl = 2 * N * N + N, o_cr = 2 * N * N + 4 * N,
+                o_ci = 2 * N * N + 4 * N + M;
+  constexpr int E = ent_re(N, A, B);
+  const int lane = c.lane;
+  auto xe = [&](int e) -> C {
+    if constexpr (X0SRC)
+      return e < N * N ? static_cast<C>(c.x0[e]) : C(0);
+    else
+      return static_cast<C>(c.sx[e * kTile + lane]);
+  };
+  // Coherent part: s = sum_k H_Ak X_kB - X_Ak H_kB; contribution -i s.
+  C sr = C(0), si = C(0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const C hak = static_cast<C>(c.P[A * N + k]);
+    const C hkb = static_cast<C>(c.P[k * N + B]);
+    const C xkb_r = xe(ent_re(N, k, B));
+    const C xkb_i = static_cast<C>(ent_sg(k, B)) * xe(ent_im(N, k, B));
+    const C xak_r = xe(ent_re(N, A, k));
+    const C xak_i = static_cast<C>(ent_sg(A, k)) * xe(ent_im(N, A, k));
+    sr += hak * xkb_r - xak_r * hkb;
+    si += hak * xkb_i - xak_i * hkb;
+  }
+  C ar = si, ai = -sr;
+  const C xr = xe(E), xi = xe(ent_im(N, A, B));
+  C dec = static_cast<C>(c.damp) + static_cast<C>(c.P[o_hg + A]) + static_cast<C>(c.P[o_hg + B]);
+  if constexpr (A != B) dec += static_cast<C>(c.P[o_dl + A]) + static_cast<C>(c.P[o_dl + B]);
+  ar -= dec * xr;
+  ai -= dec * xi;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int ma = A * KP + k;
+    const int mb = B * KP + k;
+    if constexpr (A != B) {
+      // Deeper neighbours: + i Y (mode of site A) - i Y (mode of site B),
+      // weighted by zero where the neighbour is missing.
+      const C fa = c.sup[ma * kTile + lane] >= 0 ? C(1) : C(0);
+      const C fb = c.sup[mb * kTile + lane] >= 0 ? C(1) : C(0);
+      ar += fb * L.ybi[k] - fa * L.yai[k];
+      ai += fa * L.yar[k] - fb * L.ybr[k];
+    }
+    // Shallower neighbours: + i n c Z (site A) - i n conj(c) Z (site B).
+    const C na = static_cast<C>(c.socc[ma * kTile + lane]);
+    const C nb = static_cast<C>(c.socc[mb * kTile + lane]);
+    const C car = na * static_cast<C>(c.P[o_cr + ma]), cai = na * static_cast<C>(c.P[o_ci + ma]);
+    const C cbr = nb * static_cast<C>(c.P[o_cr + mb]), cbi = nb * static_cast<C>(c.P[o_ci + mb]);
+    const C zai = (A == B) ? C(0) : L.zai[k];
+    const C zbi = (A == B) ? C(0) : L.zbi[k];
+    // i (car + i cai) z_a = -(cai zar + car zai) + i (car zar - cai zai)
+    ar -= cai * L.zar[k] + car * zai;
+    ai += car * L.zar[k] - cai * zai;
+    // -i (cbr - i cbi) z_b = (cbr zbi - cbi zbr) - i (cbr zbr + cbi zbi)
+    ar += cbr * zbi - cbi * L.zbr[k];
+    ai -= cbr * L.zbr[k] + cbi * zbi;
+  }
+  // RK4 stage: out = y + coef * rhs (at stage 0 the state planes are the
+  // stage input, so the loaded state equals the tile).
+  const C coef = static_cast<C>(c.coef);
+  const C nr = L.str + coef * ar;
+  const C ni = ((A == B) ? C(0) : L.sti) + coef * ai;
+  if constexpr (X0SRC) {
+    c.out0[E] = nr;
+    if constexpr (A != B) c.out0[E + 1] = ni;
+  }
+  const uint32_t oi = static_cast<uint32_t>(c.i) * sizeof(T);
+  st_off(c.Out + E * c.S, oi, static_cast<T>(nr));
+  if constexpr (A != B) st_off(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
+}
+
+// One chunk of wave G's elements (element indices OFF + K): all global loads
+// first, then arithmetic and stores.
+template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool X0SRC, int... K>
+__device__ __forceinline__ void tile_chunk(const TileCtx<T> &c, std::integer_sequence<int, K...>) {
+  ElemLoads<C, KP> L[sizeof...(K)];
+  (tile_load<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, X0SRC>(
+       c, L[K]),
+   ...);
+  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, X0SRC>(
+       c, L[K]),
+   ...);
+}
+
+template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool X0SRC>
+__device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
+  constexpr int P = N * (N + 1) / 2;
+  constexpr int count = (P - G + W - 1) / W;
+  constexpr int CH = HEOM_TILE_CHUNK;
+  if constexpr (OFF < count) {
+    constexpr int len = (count - OFF < CH) ? count - OFF : CH;
+    tile_chunk<N, KP, G, W, OFF, C, T, X0SRC>(c, std::make_integer_sequence<int, len>{});
+    tile_chunks<N, KP, G, W, OFF + CH, C, T, X0SRC>(c);
+  }
+}
+
+// Elements G, G + W, ... of every ADO of the tile (wave G of W).
+template <int N, int KP, int W, typename C, typename T, bool X0SRC, int G = 0>
+__device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
+  if constexpr (G < W) {
+    if (wave == G)
+      tile_chunks<N, KP, G, W, 0, C, T, X0SRC>(c);
+    else
+      tile_dispatch<N, KP, W, C, T, X0SRC, G + 1>(wave, c);
+  }
+}
+
+template <int N, int KP, typename T>
+__global__ void __launch_bounds__(64 * tile_waves_for(N), HEOM_TILE_MIN_WAVES_PER_SIMD)
+    stage_tile(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
+               double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
+  constexpr int N2 = N * N;
+  constexpr int M = N * KP;
+  constexpr int W = tile_waves_for(N);
+  constexpr bool MIXED = sizeof(T) == 4;
+  __shared__ T sx[(N2 + 1) * kTile];
+  __shared__ int32_t sup[M * kTile];
+  __shared__ int32_t sdn[M * kTile];
+  __shared__ uint8_t socc[M * kTile];
+
+  const WorkItem w = work[blockIdx.x];
+  const InstDesc &d = descs[w.inst];
+  const StageBufs bufs = stage_bufs(d, stage);
+  const int64_t S = d.stride;
+  const int lane = threadIdx.x & (kTile - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i = static_cast<int64_t>(w.first) + lane;
+  const bool valid = i < d.n_ados;
+  const HEOM_GLOBAL T *X = gmem(static_cast<const T *>(bufs.x));
+  const HEOM_GLOBAL int32_t *up = gmem(d.up);
+  const HEOM_GLOBAL int32_t *dn = gmem(d.down);
+  const HEOM_GLOBAL uint8_t *oc = gmem(d.occ);
+  // Stage the tile: wave w loads planes w, w + W, ... (a compile-time count,
+  // clamped in bounds, so that every load is issued before the first wait).
+  const int64_t ic = valid ? i : 0;  // invalid lanes load ADO 0 and store defaults
+  constexpr int RX = (N2 + W - 1) / W;
+  constexpr int RM = (M + W - 1) / W;
+  T vx[RX];
+  int32_t vu[RM], vd[RM];
+  uint8_t vo[RM];
+  const uint32_t ic4 = static_cast<uint32_t>(ic) * 4u;
+#pragma unroll
+  for (int r = 0; r < RX; ++r) {
+    const int e = min(wave + r * W, N2 - 1);
+    vx[r] = ld_off(X + e * S, static_cast<uint32_t>(ic) * static_cast<uint32_t>(sizeof(T)));
+  }
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    const int m = min(wave + r * W, M - 1);
+    vu[r] = ld_off(up + m * S, ic4);
+    vd[r] = ld_off(dn + m * S, ic4);
+    vo[r] = ld_off(oc + m * S, static_cast<uint32_t>(ic));
+  }
+#pragma unroll
+  for (int r = 0; r < RX; ++r) {
+    const int e = wave + r * W;
+    if (e < N2) sx[e * kTile + lane] = valid ? vx[r] : T(0);
+  }
+  if (wave == 0) sx[N2 * kTile + lane] = T(0);
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    const int m = wave + r * W;
+    if (m < M) {
+      sup[m * kTile + lane] = valid ? vu[r] : -1;
+      sdn[m * kTile + lane] = valid ? vd[r] : -1;
+      socc[m * kTile + lane] = valid ? vo[r] : 0;
+    }
+  }
+  __syncthreads();
+  if (!valid) return;  // no barrier below
+  const HEOM_CONST double *P = cmem(d.params);
+  double damp = 0.0;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    damp += static_cast<double>(socc[m * kTile + lane]) * P[2 * N * N + 4 * N + 2 * M + m];
+  TileCtx<T> ctx{P,
+                 sx,
+                 sup,
+                 sdn,
+                 socc,
+                 X,
+                 gmem(static_cast<const T *>(bufs.y)),
+                 gmem(static_cast<T *>(bufs.out)),
+                 gmem(bufs.x0),
+                 gmem(bufs.y0),
+                 gmem(bufs.out0),
+                 S,
+                 i,
+                 lane,
+                 damp,
+                 coef};
+  tile_dispatch<N, KP, W, T, T, false>(wave, ctx);
+  const bool is0 = (i == 0);
+  if constexpr (MIXED) {
+    // sigma_0 again, in FP64 from its FP64 copy; these writes follow the FP32
+    // ones above in program order, so they are the ones that remain.
+    if (is0) tile_dispatch<N, KP, W, double, T, true>(wave, ctx);
+  }
+  if (is0 && wave == 0) {
+    scalar_update(d, bufs, N, coef, [&](int s) {
+      if constexpr (MIXED)
+        return bufs.x0[s];
+      else
+        return static_cast<double>(sx[s * kTile + lane]);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Initialisation and snapshot kernels.
 // ---------------------------------------------------------------------------
 
@@ -502,28 +892,47 @@ __global__ void snapshot(const InstDesc *__restrict__ descs, int n_inst, int slo
 
 typedef void (*StageKernel)(const InstDesc *, const WorkItem *, int, double, int);
 
+#define HEOM_FOR_EACH_FIXED(X) \
+  X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) \
+  X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2)
+
 template <typename T>
-static StageKernel fixed_kernel(int N, int KP) {
+static StageKernel lane_kernel(int N, int KP) {
 #define HEOM_CASE(n, kp) \
   if (N == n && KP == kp) return &stage_fixed<n, kp, T>;
-  HEOM_CASE(1, 1) HEOM_CASE(2, 1) HEOM_CASE(3, 1) HEOM_CASE(4, 1)
-  HEOM_CASE(5, 1) HEOM_CASE(6, 1) HEOM_CASE(7, 1) HEOM_CASE(8, 1)
-  HEOM_CASE(1, 2) HEOM_CASE(2, 2) HEOM_CASE(3, 2) HEOM_CASE(4, 2)
-  HEOM_CASE(5, 2) HEOM_CASE(6, 2) HEOM_CASE(7, 2) HEOM_CASE(8, 2)
+  HEOM_FOR_EACH_FIXED(HEOM_CASE)
 #undef HEOM_CASE
   return nullptr;
 }
 
-bool has_fixed_kernel(int N, int KP) { return fixed_kernel<double>(N, KP) != nullptr; }
+template <typename T>
+static StageKernel tile_kernel(int N, int KP) {
+#define HEOM_CASE(n, kp) \
+  if (N == n && KP == kp) return &stage_tile<n, kp, T>;
+  HEOM_FOR_EACH_FIXED(HEOM_CASE)
+#undef HEOM_CASE
+  return nullptr;
+}
 
-hipError_t launch_stage(bool fixed, bool mixed, int N, int KP, const InstDesc *descs,
+bool has_fixed_kernel(int N, int KP) { return lane_kernel<double>(N, KP) != nullptr; }
+
+int tile_threads(int N) { return 64 * tile_waves_for(N); }
+
+hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
                         const WorkItem *work, int n_items, int block, int stage, double coef,
                         int hist_slot, hipStream_t stream) {
-  StageKernel k;
-  if (fixed)
-    k = mixed ? fixed_kernel<float>(N, KP) : fixed_kernel<double>(N, KP);
-  else
-    k = mixed ? &stage_generic<float> : &stage_generic<double>;
+  StageKernel k = nullptr;
+  switch (kind) {
+    case KernelKind::kTile:
+      k = mixed ? tile_kernel<float>(N, KP) : tile_kernel<double>(N, KP);
+      break;
+    case KernelKind::kLane:
+      k = mixed ? lane_kernel<float>(N, KP) : lane_kernel<double>(N, KP);
+      break;
+    case KernelKind::kGeneric:
+      k = mixed ? &stage_generic<float> : &stage_generic<double>;
+      break;
+  }
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(n_items), dim3(block), 0, stream, descs, work, stage, coef, hist_slot);
   return hipGetLastError();

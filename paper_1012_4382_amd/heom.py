@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libheom.so")
+# HEOM_LIB selects another build of the same library (for A/B measurements).
+LIB_PATH = os.environ.get("HEOM_LIB") or os.path.join(_HERE, "libheom.so")
 
 HEOM_OK = 0
 HEOM_E_INVALID = -1
@@ -27,6 +28,8 @@ HEOM_FP64 = 0
 HEOM_FP32_MIXED = 1
 HEOM_RESUME = 1
 HEOM_GENERIC_KERNEL = 2
+HEOM_LANE_KERNEL = 4
+KERNELS = {"auto": 0, "generic": HEOM_GENERIC_KERNEL, "lane": HEOM_LANE_KERNEL}
 
 PRECISIONS = {"fp64": HEOM_FP64, "fp32": HEOM_FP32_MIXED, HEOM_FP64: HEOM_FP64,
               HEOM_FP32_MIXED: HEOM_FP32_MIXED}
@@ -213,13 +216,13 @@ def _ws_args(ws):
 
 def propagate(h: Hierarchy, rho0, dt_fs: float, n_steps: int, record_every: int = 1,
               precision="fp64", workspace=None, stream=None, resume: bool = False,
-              generic: bool = False, want_rho: bool = True):
-    """Runs heom_propagate.  Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
+              kernel: str = "auto", want_rho: bool = True):
+    """Runs heom_propagate (kernel: "auto", or the diagnostic "lane" / "generic").  Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(h.workspace_bytes[prec])
     ptr, nbytes = _ws_args(workspace)
-    flags = (HEOM_RESUME if resume else 0) | (HEOM_GENERIC_KERNEL if generic else 0)
+    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel]
     r0 = None
     if rho0 is not None:
         r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
@@ -243,14 +246,14 @@ def batch_workspace_bytes(hs, precision="fp64") -> int:
 
 def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1,
                     precision="fp64", workspace=None, stream=None, resume: bool = False,
-                    generic: bool = False, want_rho: bool = True):
+                    kernel: str = "auto", want_rho: bool = True):
     """Runs heom_propagate_batch.  Returns (list of rho | None, sinks [n, 3], workspace)."""
     n = len(hs)
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(batch_workspace_bytes(hs, precision))
     ptr, nbytes = _ws_args(workspace)
-    flags = (HEOM_RESUME if resume else 0) | (HEOM_GENERIC_KERNEL if generic else 0)
+    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel]
     DP = ctypes.POINTER(ctypes.c_double)
     keep = []
     r0 = (DP * n)()

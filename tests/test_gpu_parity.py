@@ -52,12 +52,15 @@ def _oracle_state_by_multi(sys, depth, sig):
 
 # --- FP64 trajectories ---------------------------------------------------------
 
-@pytest.mark.parametrize("generic", [False, True])
-def test_dimer_full_trajectory_and_state(generic):
+KERNELS = ["auto", "lane", "generic"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_dimer_full_trajectory_and_state(kernel):
     w = workloads.dimer()
-    _say(f"case: dimer N=2 D=4 1000 steps generic={generic}")
+    _say(f"case: dimer N=2 D=4 1000 steps kernel={kernel}")
     h = heom.Hierarchy(w["system"], w["depth"])
-    rho, sinks, ws = heom.propagate(h, w["rho0"], w["dt"], w["steps"], generic=generic)
+    rho, sinks, ws = heom.propagate(h, w["rho0"], w["dt"], w["steps"], kernel=kernel)
     ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], want_state=True)
     assert _rel(rho, ref["rho"]) <= FP64_TOL
     # Every ADO, matched by multi-index.
@@ -72,14 +75,14 @@ def test_dimer_full_trajectory_and_state(generic):
     assert abs(rho[-1, 0, 0] - 1.0) > 0.05 and abs(rho[-1, 0, 1]) > 1e-3
 
 
-@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("site", [1, 6])
-def test_fmo_like_with_sinks_reduced_depth(generic, site):
+def test_fmo_like_with_sinks_reduced_depth(kernel, site):
     w = workloads.fmo_like(seed=0, site=site, depth=3, steps=2000)
-    _say(f"case: fmo_like N=7 D=3 site={site} 2000 steps generic={generic}")
+    _say(f"case: fmo_like N=7 D=3 site={site} 2000 steps kernel={kernel}")
     h = heom.Hierarchy(w["system"], w["depth"])
     rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=10,
-                                   generic=generic)
+                                   kernel=kernel)
     ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=10)
     assert _rel(rho, ref["rho"]) <= FP64_TOL
     assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
@@ -109,13 +112,15 @@ def test_fmo_like_full_size_sampled_and_invariants():
     assert 0.05 < sinks[0] < 1.0
 
 
-def test_matsubara_term_sweep_shape():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_matsubara_term_sweep_shape(kernel):
     """One Matsubara term per bath (14 modes), depth 3: 680 ADOs, 1000 steps."""
     w = workloads.sweep_instance(0)
     w["depth"] = 3
-    _say("case: sweep instance 0, N=7 K=1 D=3 680 ADOs, 1000 steps")
+    _say(f"case: sweep instance 0, N=7 K=1 D=3 680 ADOs, 1000 steps kernel={kernel}")
     h = heom.Hierarchy(w["system"], w["depth"])
-    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=5)
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=5,
+                                   kernel=kernel)
     ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=5)
     assert _rel(rho, ref["rho"]) <= FP64_TOL
     assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
@@ -158,13 +163,14 @@ def test_generic_kernel_larger_sites(N, depth, steps):
 
 # --- FP32 mixed precision ----------------------------------------------------------
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("T", [77.0, 300.0])
-def test_fp32_mixed_against_fp64_oracle(T):
+def test_fp32_mixed_against_fp64_oracle(T, kernel):
     w = workloads.fmo_like(seed=0, site=1, depth=4, T=T, steps=3000)
-    _say(f"case: fp32-mixed fmo_like N=7 D=4 T={T} 3000 steps")
+    _say(f"case: fp32-mixed fmo_like N=7 D=4 T={T} 3000 steps kernel={kernel}")
     h = heom.Hierarchy(w["system"], w["depth"])
     rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=10,
-                                   precision="fp32")
+                                   precision="fp32", kernel=kernel)
     ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=10)
     p = np.real(np.diagonal(rho, axis1=1, axis2=2))
     pr = np.real(np.diagonal(ref["rho"], axis1=1, axis2=2))
@@ -188,8 +194,9 @@ def test_fp32_mixed_full_size_sampled():
 
 # --- batching, resume, determinism ---------------------------------------------------
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_equals_single_solves(precision):
+def test_batch_equals_single_solves(precision, kernel):
     ws_ = [workloads.fmo_like(seed=s, site=site, depth=4, steps=300) for s in (0, 1) for site in (1, 6)]
     ws_.append(workloads.sweep_instance(3))
     ws_[-1]["depth"], ws_[-1]["steps"] = 2, 300
@@ -198,9 +205,10 @@ def test_batch_equals_single_solves(precision):
     _say(f"case: batch of {len(ws_)} mixed instances vs single solves ({precision})")
     hs = [heom.Hierarchy(w["system"], w["depth"]) for w in ws_]
     rhos, sinks, _ = heom.propagate_batch(hs, [w["rho0"] for w in ws_], 1.0, 300, record_every=3,
-                                          precision=precision)
+                                          precision=precision, kernel=kernel)
     for k, (h, w) in enumerate(zip(hs, ws_)):
-        r1, s1, _ = heom.propagate(h, w["rho0"], 1.0, 300, record_every=3, precision=precision)
+        r1, s1, _ = heom.propagate(h, w["rho0"], 1.0, 300, record_every=3, precision=precision,
+                                   kernel=kernel)
         assert np.array_equal(rhos[k], r1), k
         assert np.array_equal(sinks[k], s1), k
 
