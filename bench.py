@@ -34,7 +34,44 @@ def _parse():
     p.add_argument("--no-variants", action="store_true")
     p.add_argument("--kernel", default="auto", choices=["auto", "lane", "generic"],
                    help="stage kernel (lane and generic are diagnostic)")
+    p.add_argument("--no-sizing", action="store_true",
+                   help="skip the HBM-resident N=7, depth-16 measurement")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 256 MiB device copy (reference for traffic counters)")
     return p.parse_args()
+
+
+def _stage_kernel_timing(heom, torch, hs, rho0s, stream, kernel, precision="fp64", steps=500):
+    """Average stage-kernel duration (ms) from HIP events on the library's
+    stream over a run without history records, and the run's ADO-steps/s."""
+    ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, precision))
+    heom.propagate_batch(hs, rho0s, 1.0, 20, record_every=20, workspace=ws, stream=stream,
+                         want_rho=False, kernel=kernel, precision=precision)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    heom.propagate_batch(hs, rho0s, 1.0, steps, record_every=steps, workspace=ws, stream=stream,
+                         want_rho=False, kernel=kernel, precision=precision)
+    ev1.record(stream)
+    ev1.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    ados = sum(h.n_ados for h in hs)
+    return total_ms / (4 * steps), ados * steps / (total_ms * 1e-3)
+
+
+def _sizing(heom, torch, workloads, stream, kernel):
+    """The paper's largest hierarchy shape: 7 sites, depth 16 (245157 ADOs), one
+    solve, FP64 and FP32-mixed; state well beyond the 256 MB Infinity Cache."""
+    w = workloads.fmo_like(seed=0, site=1, depth=16, steps=200)
+    h = heom.Hierarchy(w["system"], w["depth"])
+    out = {"workload": "fmo_like_7site_depth16_single_solve", "n_ados": h.n_ados}
+    for prec, s in (("fp64", 8), ("fp32", 4)):
+        k_ms, rate = _stage_kernel_timing(heom, torch, [h], [w["rho0"]], stream, kernel, prec,
+                                          steps=100)
+        bpl = h.n_ados * (11.0 / 4.0) * h.N * h.N * s
+        out[prec] = {"ado_steps_per_s": rate, "kernel_avg_us": k_ms * 1e3,
+                     "achieved_GBps": bpl / (k_ms * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": bpl / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def _cpu_baseline(w, target_s=12.0):
@@ -102,16 +139,7 @@ def main():
 
     # Dominant kernel: the fused RK4 stage.  Average duration per launch from
     # HIP events on the library's stream over a run without history records.
-    n_launch_steps = 500
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    heom.propagate_batch(hs, rho0s, 1.0, 20, record_every=20, workspace=ws, stream=stream,
-                         want_rho=False, kernel=args.kernel)
-    ev0.record(stream)
-    heom.propagate_batch(hs, rho0s, 1.0, n_launch_steps, record_every=n_launch_steps,
-                         workspace=ws, stream=stream, want_rho=False, kernel=args.kernel)
-    ev1.record(stream)
-    ev1.synchronize()
-    kernel_ms = ev0.elapsed_time(ev1) / (4 * n_launch_steps)
+    kernel_ms, _ = _stage_kernel_timing(heom, torch, hs, rho0s, stream, args.kernel)
     # Algorithmic bytes per launch: the nested RK4 form moves 11 packed ADOs
     # (N*N reals) per step, 11/4 per stage on average.
     bytes_per_launch = total_ados * (11.0 / 4.0) * N * N * 8
@@ -161,6 +189,17 @@ def main():
         result["variants"] = {"fp64_single_solve_ado_steps_per_s": plain,
                               "fp32_mixed_batched_ado_steps_per_s": fp32,
                               "fp64_batched_over_single": value / plain}
+    if not args.no_sizing:
+        result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
+    if args.copy_calibration:
+        # A plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
+        # kernel calibrate the traffic counters of the stage kernel.
+        src = torch.ones(32 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(batch[0])
     print(json.dumps(result), flush=True)

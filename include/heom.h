@@ -59,8 +59,10 @@ enum {
   HEOM_RESUME = 1,          /* continue from the state held in the workspace   */
   HEOM_GENERIC_KERNEL = 2,  /* diagnostic: use the generic stage kernel even
                                where a specialised one exists                   */
-  HEOM_LANE_KERNEL = 4      /* diagnostic: use the one-lane-per-ADO specialised
+  HEOM_LANE_KERNEL = 4,     /* diagnostic: use the one-lane-per-ADO specialised
                                kernel instead of the LDS-tiled one (N <= 8)     */
+  HEOM_NO_GRAPH = 8         /* diagnostic: launch every stage kernel directly
+                               instead of replaying captured graphs of steps    */
 };
 
 typedef struct heom_hierarchy heom_hierarchy; /* opaque, library-owned */
@@ -156,6 +158,35 @@ int heom_propagate_batch(heom_hierarchy *const *hs, int32_t n, int precision, in
                          const double *const *rho0s, double dt_fs, int64_t n_steps,
                          int64_t record_every, void *d_workspace, size_t workspace_bytes,
                          void *hip_stream, double *const *rho_outs, double *const *sinks_outs);
+
+/* Device scratch needed by heom_advance_slots for the n hierarchies hs[]
+ * (the launch's descriptors and work list). */
+int heom_slots_scratch_bytes(heom_hierarchy *const *hs, int32_t n, size_t *bytes);
+
+/* Advances n independent runs by n_steps RK4 steps of dt_fs, each run held in
+ * its own workspace, with one kernel launch per RK4 stage (per distinct kernel
+ * variant) for all of them.  This lets a caller batch runs that start and
+ * finish at different times without moving their state (continuous batching).
+ *   d_workspaces[i]     device memory laid out as for heom_propagate on hs[i]
+ *                       (at least workspace_bytes_* of heom_hierarchy_info for
+ *                       `precision`), workspace_bytes[i] its size; distinct
+ *   start[i]            1: initialise run i from rho0s[i] (N*N complex
+ *                       Hermitian); 0: continue the run held in its workspace
+ *                       (as HEOM_RESUME; rho0s[i] may be NULL)
+ *   flags               HEOM_GENERIC_KERNEL, HEOM_LANE_KERNEL, HEOM_NO_GRAPH
+ *   d_scratch           at least heom_slots_scratch_bytes(hs, n) bytes, 256-byte
+ *                       aligned; its contents are not needed after the call
+ *   rho_out[i]          host N*N complex: sigma_0 after the last step, or NULL
+ *   sinks_out[i]        host [3] = {P_trap, P_recomb, Q}, or NULL
+ * Each run's arithmetic does not depend on the others: its results equal
+ * those of heom_propagate on that run alone.  A workspace advanced here can be
+ * continued by heom_propagate with HEOM_RESUME and vice versa.
+ * Errors as heom_propagate. */
+int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
+                       void *const *d_workspaces, const size_t *workspace_bytes,
+                       const int32_t *start, const double *const *rho0s, double dt_fs,
+                       int64_t n_steps, void *d_scratch, size_t scratch_bytes, void *hip_stream,
+                       double *const *rho_out, double *const *sinks_out);
 
 /* Energy-transfer efficiency (eq:eta) and mean trapping time (eq:trappingtime)
  * for an excitation starting in rho0.

@@ -34,7 +34,8 @@
 //   * Matsubara terms (not written in the paper) follow from the Drude-Lorentz
 //     spectral density eq:gamma: nu_k = 2 pi k kT,
 //     c_k = 4 lambda gamma kT nu_k / (nu_k^2 - gamma^2);
-//   * the low-temperature correction ("lowest-order quantum correction",
+//   * the low-temperature correction (the first quantum correction to the
+//     high-temperature bath statistics that the paper applies,
 //     section "Trapping time for different temperatures") is the Markovian
 //     residual -Delta_s [V_s,[V_s, .]] on every ADO, with
 //     Delta_s = 2 lambda kT/gamma - lambda cot(gamma/2kT) - sum_{k<=K} c_k/nu_k;

@@ -10,8 +10,8 @@
 // sequence with small gaps, so that lanes handling consecutive ADOs gather
 // their neighbours from nearly contiguous addresses.
 //
-// Each ADO is linked to its neighbours n +- e_m (Appendix B: "each sigma-matrix
-// is connected to 2N neighbours ... stored in GPU memory"); here the links are
+// Each ADO is linked to its neighbours n +- e_m (Appendix B keeps these links
+// in device memory as linked lists); here the links are
 // dense int32 tables [M][stride] (-1 where the neighbour does not exist) plus
 // the occupation n_m as uint8, laid out so that consecutive lanes read
 // consecutive entries.

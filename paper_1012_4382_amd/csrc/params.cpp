@@ -10,7 +10,8 @@
 //     high-temperature form 2*lambda*kT - i*lambda*gamma (theta after eq:M,
 //     with k_B T moved to the numerator so that the units agree);
 //   * Matsubara amplitudes 4 lambda gamma kT nu_k / (nu_k^2 - gamma^2);
-//   * low-temperature correction ("lowest-order quantum correction", section
+//   * low-temperature correction (the first quantum correction the paper applies
+//     to the high-temperature bath statistics, section
 //     "Trapping time for different temperatures"): the Matsubara terms beyond
 //     K act as a white-noise residual -Delta [V,[V, .]] with
 //     Delta = 2 lambda kT / gamma - lambda cot(gamma/2kT) - sum_{k<=K} c_k/nu_k;

@@ -88,8 +88,10 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   off = align_up(off + sizeof(Header));
   L.descs = off;
   off = align_up(off + sizeof(InstDesc) * n);
+  // Work items: stage items (at most one per 64 ADOs) and initialisation
+  // items (one per 64 ADOs).
   int64_t cap = 0;
-  for (int k = 0; k < n; ++k) cap += (hs[k]->n_ados + kPlanePad - 1) / kPlanePad;
+  for (int k = 0; k < n; ++k) cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad);
   L.work = off;
   L.work_cap = cap;
   off = align_up(off + sizeof(WorkItem) * cap);
@@ -201,6 +203,53 @@ void unpack_hermitian(int N, const double *packed, double *rho) {
   }
 }
 
+// Steps captured in one graph.
+constexpr int64_t kGraphSteps = 32;
+
+// A private stream per device and host thread, used only to capture graphs
+// (capture on the caller's stream is not possible when it is the legacy
+// default stream).  Default priority.
+int capture_stream(int device, hipStream_t *out) {
+  thread_local std::map<int, hipStream_t> streams;
+  auto it = streams.find(device);
+  if (it != streams.end()) {
+    *out = it->second;
+    return HEOM_OK;
+  }
+  hipStream_t s;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return dev_fail(e, "hipStreamCreateWithFlags");
+  streams[device] = s;
+  *out = s;
+  return HEOM_OK;
+}
+
+// A graph of k RK4 steps, destroyed with the object.
+struct StepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  template <typename Enqueue>
+  int build(int device, int64_t k, Enqueue enqueue_step) {
+    hipStream_t cap;
+    int rc = capture_stream(device, &cap);
+    if (rc) return rc;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return dev_fail(e, "hipStreamBeginCapture");
+    hipError_t launch_err = hipSuccess;
+    for (int64_t i = 0; i < k && launch_err == hipSuccess; ++i) launch_err = enqueue_step(cap);
+    e = hipStreamEndCapture(cap, &graph);
+    if (launch_err != hipSuccess) return dev_fail(launch_err, "stage kernel (capture)");
+    if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return dev_fail(e, "hipGraphInstantiate");
+    return HEOM_OK;
+  }
+  ~StepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 struct Group {
   KernelKind kind;
   int N, KP;
@@ -208,47 +257,66 @@ struct Group {
   int64_t item_begin, n_items;
 };
 
-int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
-                   const double *const *rho0s, double dt_fs, int64_t n_steps, int64_t record_every,
-                   void *d_ws, size_t ws_bytes, void *hip_stream, double *const *rho_outs,
-                   double *const *sinks_outs) {
+// Where the device data of one call live: each instance's regions (offsets
+// relative to its own base), the headers that identify the runs held there,
+// and the descriptor array and work list of the launch.
+struct RunPlace {
+  std::vector<char *> base;       // per instance
+  std::vector<InstLayout> inst;   // per instance, relative to base
+  std::vector<char *> header;     // header regions
+  std::vector<Header> want;       // their contents for this call
+  std::vector<int> header_of;     // per instance: its header region
+  char *descs = nullptr, *work = nullptr;
+  int64_t work_cap = 0;
+};
+
+int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, double dt_fs,
+                 int64_t n_steps, int64_t record_every, int allowed_flags) {
   if (!hs || n < 1) return fail(HEOM_E_INVALID, "no hierarchies");
   for (int k = 0; k < n; ++k)
     if (!hs[k]) return fail(HEOM_E_INVALID, "NULL hierarchy handle");
   if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
     return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
-  if (flags & ~(HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL))
-    return fail(HEOM_E_INVALID, "unknown flags");
+  if (flags & ~allowed_flags) return fail(HEOM_E_INVALID, "unknown flags");
   if ((flags & HEOM_GENERIC_KERNEL) && (flags & HEOM_LANE_KERNEL))
     return fail(HEOM_E_INVALID, "HEOM_GENERIC_KERNEL and HEOM_LANE_KERNEL are exclusive");
   if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
   if (n_steps < 0) return fail(HEOM_E_INVALID, "n_steps must be >= 0");
   if (record_every < 1) return fail(HEOM_E_INVALID, "record_every must be >= 1");
-  const bool resume = (flags & HEOM_RESUME) != 0;
-  const bool mixed = precision == HEOM_FP32_MIXED;
-  const Layout L = make_layout(hs, n, precision);
-  if (!d_ws) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
-    return fail(HEOM_E_WORKSPACE, "workspace must be 256-byte aligned");
-  if (ws_bytes < L.total)
-    return fail(HEOM_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  return HEOM_OK;
+}
 
+// Propagates n instances placed as described by `place`.  start[k] = 1
+// initialises instance k from rho0s[k]; 0 continues the run held there.
+int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const int32_t *start,
+             const double *const *rho0s, double dt_fs, int64_t n_steps, int64_t record_every,
+             const RunPlace &place, void *hip_stream, double *const *rho_outs,
+             double *const *sinks_outs) {
+  const bool mixed = precision == HEOM_FP32_MIXED;
   // Packed initial states (validated before any device work).
   std::vector<std::vector<double>> params(n);
   for (int k = 0; k < n; ++k) {
     params[k] = hs[k]->params;
-    if (!resume) {
+    if (start[k]) {
       if (!rho0s || !rho0s[k]) return fail(HEOM_E_INVALID, "rho0 is NULL");
       const ParamOffsets o = param_offsets(hs[k]->N, hs[k]->M);
       int rc = pack_hermitian(hs[k]->N, rho0s[k], params[k].data() + o.rho0);
       if (rc) return rc;
     }
   }
+  // A header region is either started or continued as a whole.
+  std::vector<int> hdr_start(place.header.size(), -1);
+  for (int k = 0; k < n; ++k) {
+    int &hs_ = hdr_start[place.header_of[k]];
+    const int s = start[k] ? 1 : 0;
+    if (hs_ >= 0 && hs_ != s)
+      return fail(HEOM_E_INVALID, "instances sharing a workspace must all start or all resume");
+    hs_ = s;
+  }
 
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   int device = 0;
   HEOM_HIP(hipGetDevice(&device), "hipGetDevice");
-  char *ws = static_cast<char *>(d_ws);
 
   // Descriptors and work list.
   std::vector<InstDesc> descs(n);
@@ -256,7 +324,8 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
     heom_hierarchy::DeviceTables t;
     int rc = ensure_device_tables(hs[k], device, &t);
     if (rc) return rc;
-    const InstLayout &I = L.inst[k];
+    char *ws = place.base[k];
+    const InstLayout &I = place.inst[k];
     InstDesc &d = descs[k];
     d.y = ws + I.y;
     d.a = ws + I.a;
@@ -309,40 +378,47 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
     g.n_items = static_cast<int64_t>(items.size()) - g.item_begin;
     groups.push_back(g);
   }
-  if (static_cast<int64_t>(items.size()) > L.work_cap)
+  // Initialisation items (64 ADOs each) of the instances that start here.
+  const int64_t init_begin = static_cast<int64_t>(items.size());
+  for (int k = 0; k < n; ++k)
+    if (start[k])
+      for (int64_t first = 0; first < hs[k]->n_ados; first += kPlanePad)
+        items.push_back({k, static_cast<int32_t>(first)});
+  const int64_t n_init = static_cast<int64_t>(items.size()) - init_begin;
+  if (static_cast<int64_t>(items.size()) > place.work_cap)
     return fail(HEOM_E_WORKSPACE, "work list exceeds its workspace region");
 
-  int64_t total_ados = 0;
-  for (int k = 0; k < n; ++k) total_ados += hs[k]->n_ados;
-  Header hdr = {kMagic, n, precision, total_ados};
-  if (resume) {
+  // Continued runs must be the runs these hierarchies left in the workspace.
+  for (size_t r = 0; r < place.header.size(); ++r) {
+    if (hdr_start[r] != 0) continue;
     Header cur;
-    HEOM_HIP(hipMemcpyAsync(&cur, ws + L.header, sizeof(Header), hipMemcpyDeviceToHost, stream),
+    HEOM_HIP(hipMemcpyAsync(&cur, place.header[r], sizeof(Header), hipMemcpyDeviceToHost, stream),
              "hipMemcpyAsync(header)");
     HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
-    if (std::memcmp(&cur, &hdr, sizeof(Header)) != 0)
+    if (std::memcmp(&cur, &place.want[r], sizeof(Header)) != 0)
       return fail(HEOM_E_WORKSPACE, "workspace does not hold a run of these hierarchies");
   }
-  HEOM_HIP(hipMemcpyAsync(ws + L.descs, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice,
+  HEOM_HIP(hipMemcpyAsync(place.descs, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice,
                           stream),
            "hipMemcpyAsync(descs)");
-  HEOM_HIP(hipMemcpyAsync(ws + L.work, items.data(), sizeof(WorkItem) * items.size(),
+  HEOM_HIP(hipMemcpyAsync(place.work, items.data(), sizeof(WorkItem) * items.size(),
                           hipMemcpyHostToDevice, stream),
            "hipMemcpyAsync(work)");
   for (int k = 0; k < n; ++k)
-    HEOM_HIP(hipMemcpyAsync(ws + L.inst[k].params, params[k].data(),
+    HEOM_HIP(hipMemcpyAsync(place.base[k] + place.inst[k].params, params[k].data(),
                             sizeof(double) * params[k].size(), hipMemcpyHostToDevice, stream),
              "hipMemcpyAsync(params)");
-  const InstDesc *d_descs = reinterpret_cast<const InstDesc *>(ws + L.descs);
-  const WorkItem *d_work = reinterpret_cast<const WorkItem *>(ws + L.work);
-  if (!resume) {
-    for (const Group &g : groups)
-      HEOM_HIP(launch_init(mixed, d_descs, d_work + g.item_begin, static_cast<int>(g.n_items),
-                           g.ados_per_item, stream),
-               "init kernel");
-    HEOM_HIP(hipMemcpyAsync(ws + L.header, &hdr, sizeof(Header), hipMemcpyHostToDevice, stream),
-             "hipMemcpyAsync(header)");
-  }
+  const InstDesc *d_descs = reinterpret_cast<const InstDesc *>(place.descs);
+  const WorkItem *d_work = reinterpret_cast<const WorkItem *>(place.work);
+  if (n_init > 0)
+    HEOM_HIP(launch_init(mixed, d_descs, d_work + init_begin, static_cast<int>(n_init),
+                         static_cast<int>(kPlanePad), stream),
+             "init kernel");
+  for (size_t r = 0; r < place.header.size(); ++r)
+    if (hdr_start[r] == 1)
+      HEOM_HIP(hipMemcpyAsync(place.header[r], &place.want[r], sizeof(Header),
+                              hipMemcpyHostToDevice, stream),
+               "hipMemcpyAsync(header)");
 
   bool want_rho = false;
   for (int k = 0; rho_outs && k < n; ++k) want_rho = want_rho || rho_outs[k] != nullptr;
@@ -355,7 +431,7 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
       if (!rho_outs[k]) continue;
       const size_t rec_len = static_cast<size_t>(hs[k]->N) * hs[k]->N + kScalars;
       host_ring[k].resize(rec_len * slot);
-      HEOM_HIP(hipMemcpyAsync(host_ring[k].data(), ws + L.inst[k].hist,
+      HEOM_HIP(hipMemcpyAsync(host_ring[k].data(), place.base[k] + place.inst[k].hist,
                               sizeof(double) * rec_len * slot, hipMemcpyDeviceToHost, stream),
                "hipMemcpyAsync(history)");
     }
@@ -383,16 +459,33 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
     ++slot;
   }
   const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
-  for (int64_t step = 1; step <= n_steps; ++step) {
-    const bool rec = want_rho && (step % record_every == 0);
-    for (int s = 0; s < 4; ++s) {
+  // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.
+  auto enqueue_step = [&](hipStream_t s) -> hipError_t {
+    for (int st = 0; st < 4; ++st)
       for (const Group &g : groups) {
-        HEOM_HIP(launch_stage(g.kind, mixed, g.N, g.KP, d_descs, d_work + g.item_begin,
-                              static_cast<int>(g.n_items), g.threads, s, coef[s], -1, stream),
-                 "stage kernel");
+        hipError_t e = launch_stage(g.kind, mixed, g.N, g.KP, d_descs, d_work + g.item_begin,
+                                    static_cast<int>(g.n_items), g.threads, st, coef[st], -1, s);
+        if (e != hipSuccess) return e;
       }
-    }
-    if (rec) {
+    return hipSuccess;
+  };
+  // Runs of kGraphSteps steps are replayed from one captured graph, which
+  // removes the host launch cost of each stage kernel.
+  StepGraph graph;
+  const bool use_graph = (flags & HEOM_NO_GRAPH) == 0 && n_steps >= kGraphSteps;
+  if (use_graph) {
+    int rc = graph.build(device, kGraphSteps, enqueue_step);
+    if (rc) return rc;
+  }
+  int64_t step = 0;
+  while (step < n_steps) {
+    // Steps until the next record (or the end).
+    int64_t run = n_steps - step;
+    if (want_rho) run = std::min(run, record_every - step % record_every);
+    for (; use_graph && run >= kGraphSteps; run -= kGraphSteps, step += kGraphSteps)
+      HEOM_HIP(hipGraphLaunch(graph.exec, stream), "hipGraphLaunch");
+    for (; run > 0; --run, ++step) HEOM_HIP(enqueue_step(stream), "stage kernel");
+    if (want_rho && step % record_every == 0) {
       HEOM_HIP(launch_snapshot(mixed, d_descs, n, slot, stream), "snapshot kernel");
       ++slot;
       if (slot == kRingRecords) {
@@ -412,7 +505,7 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
   if (want_sinks)
     for (int k = 0; k < n; ++k)
       if (sinks_outs[k])
-        HEOM_HIP(hipMemcpyAsync(sc.data() + kScalars * k, ws + L.inst[k].sc_y,
+        HEOM_HIP(hipMemcpyAsync(sc.data() + kScalars * k, place.base[k] + place.inst[k].sc_y,
                                 sizeof(double) * kScalars, hipMemcpyDeviceToHost, stream),
                  "hipMemcpyAsync(scalars)");
   HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
@@ -421,6 +514,56 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
       if (sinks_outs[k])
         for (int q = 0; q < 3; ++q) sinks_outs[k][q] = sc[kScalars * k + q];
   return HEOM_OK;
+}
+
+Header header_for(heom_hierarchy *const *hs, int n, int precision) {
+  int64_t total = 0;
+  for (int k = 0; k < n; ++k) total += hs[k]->n_ados;
+  return Header{kMagic, n, precision, total};
+}
+
+// All instances in one workspace (heom_propagate, heom_propagate_batch).
+int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
+                   const double *const *rho0s, double dt_fs, int64_t n_steps, int64_t record_every,
+                   void *d_ws, size_t ws_bytes, void *hip_stream, double *const *rho_outs,
+                   double *const *sinks_outs) {
+  int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, record_every,
+                        HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH);
+  if (rc) return rc;
+  const Layout L = make_layout(hs, n, precision);
+  if (!d_ws) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+    return fail(HEOM_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(HEOM_E_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  char *ws = static_cast<char *>(d_ws);
+  RunPlace P;
+  P.base.assign(n, ws);
+  P.inst = L.inst;
+  P.header = {ws + L.header};
+  P.want = {header_for(hs, n, precision)};
+  P.header_of.assign(n, 0);
+  P.descs = ws + L.descs;
+  P.work = ws + L.work;
+  P.work_cap = L.work_cap;
+  const std::vector<int32_t> start(n, (flags & HEOM_RESUME) ? 0 : 1);
+  return run_impl(hs, n, precision, flags & ~HEOM_RESUME, start.data(), rho0s, dt_fs, n_steps,
+                  record_every, P, hip_stream, rho_outs, sinks_outs);
+}
+
+// Scratch of a multi-workspace launch: descriptors and work list.
+struct SlotScratch {
+  size_t descs = 0, work = 0, total = 0;
+  int64_t work_cap = 0;
+};
+SlotScratch slot_scratch(heom_hierarchy *const *hs, int n) {
+  SlotScratch s;
+  s.descs = 0;
+  size_t off = align_up(sizeof(InstDesc) * n);
+  for (int k = 0; k < n; ++k) s.work_cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad);
+  s.work = off;
+  s.total = align_up(off + sizeof(WorkItem) * s.work_cap);
+  return s;
 }
 
 }  // namespace
@@ -550,6 +693,75 @@ int heom_propagate_batch(heom_hierarchy *const *hs, int32_t n, int precision, in
     }
     return propagate_impl(hs, n, precision, flags, rho0s, dt_fs, n_steps, record_every,
                           d_workspace, workspace_bytes, hip_stream, ro.data(), so.data());
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+}
+
+int heom_slots_scratch_bytes(heom_hierarchy *const *hs, int32_t n, size_t *bytes) {
+  if (!hs || n < 1 || !bytes) return fail(HEOM_E_INVALID, "bad arguments");
+  for (int k = 0; k < n; ++k)
+    if (!hs[k]) return fail(HEOM_E_INVALID, "NULL hierarchy handle");
+  *bytes = slot_scratch(hs, n).total;
+  return HEOM_OK;
+}
+
+int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
+                       void *const *d_workspaces, const size_t *workspace_bytes,
+                       const int32_t *start, const double *const *rho0s, double dt_fs,
+                       int64_t n_steps, void *d_scratch, size_t scratch_bytes, void *hip_stream,
+                       double *const *rho_out, double *const *sinks_out) {
+  try {
+    int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, 1,
+                          HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH);
+    if (rc) return rc;
+    if (!d_workspaces || !workspace_bytes || !start)
+      return fail(HEOM_E_INVALID, "workspaces, sizes and start flags are required");
+    const SlotScratch sc = slot_scratch(hs, n);
+    if (!d_scratch || reinterpret_cast<uintptr_t>(d_scratch) % kAlign || scratch_bytes < sc.total)
+      return fail(HEOM_E_WORKSPACE, "scratch missing, misaligned or too small: need " +
+                                        std::to_string(sc.total) + " bytes");
+    RunPlace P;
+    for (int k = 0; k < n; ++k) {
+      heom_hierarchy *h = hs[k];
+      const Layout L1 = make_layout(&h, 1, precision);
+      char *ws = static_cast<char *>(d_workspaces[k]);
+      if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign || workspace_bytes[k] < L1.total)
+        return fail(HEOM_E_WORKSPACE, "workspace " + std::to_string(k) +
+                                          " missing, misaligned or too small");
+      for (int j = 0; j < k; ++j)
+        if (d_workspaces[j] == d_workspaces[k])
+          return fail(HEOM_E_INVALID, "two slots share one workspace");
+      P.base.push_back(ws);
+      P.inst.push_back(L1.inst[0]);
+      P.header.push_back(ws + L1.header);
+      P.want.push_back(header_for(&h, 1, precision));
+      P.header_of.push_back(k);
+    }
+    char *s = static_cast<char *>(d_scratch);
+    P.descs = s + sc.descs;
+    P.work = s + sc.work;
+    P.work_cap = sc.work_cap;
+    // Records: the state at the start and after the last step.
+    const int64_t rec_every = n_steps > 0 ? n_steps : 1;
+    std::vector<std::vector<double>> rec(n);
+    std::vector<double *> ro(n, nullptr), so(n, nullptr);
+    for (int k = 0; k < n; ++k) {
+      if (rho_out && rho_out[k]) {
+        rec[k].assign(4 * static_cast<size_t>(hs[k]->N) * hs[k]->N, 0.0);
+        ro[k] = rec[k].data();
+      }
+      if (sinks_out) so[k] = sinks_out[k];
+    }
+    rc = run_impl(hs, n, precision, flags, start, rho0s, dt_fs, n_steps, rec_every, P, hip_stream,
+                  ro.data(), so.data());
+    if (rc) return rc;
+    for (int k = 0; k < n; ++k)
+      if (ro[k]) {
+        const size_t len = 2 * static_cast<size_t>(hs[k]->N) * hs[k]->N;
+        std::memcpy(rho_out[k], rec[k].data() + (n_steps > 0 ? len : 0), sizeof(double) * len);
+      }
+    return HEOM_OK;
   } catch (...) {
     return fail(HEOM_E_NOMEM, "host allocation failed");
   }

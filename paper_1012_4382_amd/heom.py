@@ -29,6 +29,7 @@ HEOM_FP32_MIXED = 1
 HEOM_RESUME = 1
 HEOM_GENERIC_KERNEL = 2
 HEOM_LANE_KERNEL = 4
+HEOM_NO_GRAPH = 8
 KERNELS = {"auto": 0, "generic": HEOM_GENERIC_KERNEL, "lane": HEOM_LANE_KERNEL}
 
 PRECISIONS = {"fp64": HEOM_FP64, "fp32": HEOM_FP32_MIXED, HEOM_FP64: HEOM_FP64,
@@ -82,6 +83,10 @@ _SIGNATURES = [
     ("heom_efficiency", ctypes.c_int, [_vp, ctypes.c_int, _P(_d), _d, _d, _d, _vp, _sz, _vp,
                                        _P(EffResult)]),
     ("heom_read_state", ctypes.c_int, [_vp, ctypes.c_int, _vp, _sz, _vp, _P(_d)]),
+    ("heom_slots_scratch_bytes", ctypes.c_int, [_P(_vp), _i32, _P(_sz)]),
+    ("heom_advance_slots", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, ctypes.c_int, _P(_vp),
+                                          _P(_sz), _P(_i32), _P(_P(_d)), _d, _i64, _vp, _sz, _vp,
+                                          _P(_P(_d)), _P(_P(_d))]),
     ("heom_destroy", None, [_vp]),
     ("heom_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("heom_last_error", ctypes.c_char_p, []),
@@ -216,13 +221,13 @@ def _ws_args(ws):
 
 def propagate(h: Hierarchy, rho0, dt_fs: float, n_steps: int, record_every: int = 1,
               precision="fp64", workspace=None, stream=None, resume: bool = False,
-              kernel: str = "auto", want_rho: bool = True):
+              kernel: str = "auto", want_rho: bool = True, graphs: bool = True):
     """Runs heom_propagate (kernel: "auto", or the diagnostic "lane" / "generic").  Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(h.workspace_bytes[prec])
     ptr, nbytes = _ws_args(workspace)
-    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel]
+    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
     r0 = None
     if rho0 is not None:
         r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
@@ -246,14 +251,14 @@ def batch_workspace_bytes(hs, precision="fp64") -> int:
 
 def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1,
                     precision="fp64", workspace=None, stream=None, resume: bool = False,
-                    kernel: str = "auto", want_rho: bool = True):
+                    kernel: str = "auto", want_rho: bool = True, graphs: bool = True):
     """Runs heom_propagate_batch.  Returns (list of rho | None, sinks [n, 3], workspace)."""
     n = len(hs)
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(batch_workspace_bytes(hs, precision))
     ptr, nbytes = _ws_args(workspace)
-    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel]
+    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
     DP = ctypes.POINTER(ctypes.c_double)
     keep = []
     r0 = (DP * n)()
@@ -300,3 +305,43 @@ def read_state(h: Hierarchy, workspace, precision="fp64", stream=None):
                                      _stream_handle(stream), _dp(buf)), "heom_read_state")
     sig = buf[: 2 * h.n_ados * h.N * h.N].view(np.complex128).reshape(h.n_ados, h.N, h.N)
     return sig, buf[2 * h.n_ados * h.N * h.N:].copy()
+
+
+def slots_scratch_bytes(hs) -> int:
+    arr = (ctypes.c_void_p * len(hs))(*[h.handle.value for h in hs])
+    out = ctypes.c_size_t()
+    _check(library().heom_slots_scratch_bytes(arr, len(hs), ctypes.byref(out)),
+           "heom_slots_scratch_bytes")
+    return out.value
+
+
+def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scratch,
+                  precision="fp64", stream=None, kernel: str = "auto", graphs: bool = True,
+                  want_rho: bool = True):
+    """Runs heom_advance_slots.  Returns (list of final rho [N, N] | None, sinks [n, 3])."""
+    n = len(hs)
+    DP = ctypes.POINTER(ctypes.c_double)
+    wsp = (ctypes.c_void_p * n)(*[w.data_ptr() for w in workspaces])
+    wsb = (ctypes.c_size_t * n)(*[w.numel() * w.element_size() for w in workspaces])
+    st = (ctypes.c_int32 * n)(*[1 if s else 0 for s in start])
+    keep = []
+    r0 = (DP * n)()
+    for k in range(n):
+        if rho0s is not None and rho0s[k] is not None:
+            a = np.ascontiguousarray(np.asarray(rho0s[k], np.complex128)).view(np.float64)
+            keep.append(a)
+            r0[k] = _dp(a)
+    rhos = [np.zeros((h.N, h.N), np.complex128) for h in hs] if want_rho else None
+    sinks = np.zeros((n, 3))
+    ro, so = (DP * n)(), (DP * n)()
+    for k in range(n):
+        if rhos is not None:
+            ro[k] = _dp(rhos[k].view(np.float64))
+        so[k] = sinks[k].ctypes.data_as(DP)
+    arr = (ctypes.c_void_p * n)(*[h.handle.value for h in hs])
+    sptr, sbytes = _ws_args(scratch)
+    flags = KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
+    _check(library().heom_advance_slots(arr, n, PRECISIONS[precision], flags, wsp, wsb, st, r0,
+                                        float(dt_fs), int(n_steps), sptr, sbytes,
+                                        _stream_handle(stream), ro, so), "heom_advance_slots")
+    return rhos, sinks

@@ -296,3 +296,71 @@ def test_numeric_failure_is_reported():
     with pytest.raises(heom.HeomError) as ei:
         heom.propagate(h, w["rho0"], 400.0, 2000, record_every=100)
     assert ei.value.status == heom.HEOM_E_NUMERIC
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replays_match_direct_launches(precision):
+    """Captured graphs of steps, replayed many times with eager snapshot
+    launches and a resumed call in between, equal direct launches bitwise."""
+    w = workloads.fmo_like(seed=1, site=6, depth=4, steps=320)
+    _say(f"case: graph replays vs direct launches ({precision})")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    ref, s_ref, _ = heom.propagate(h, w["rho0"], 1.0, 640, record_every=64, precision=precision,
+                                   graphs=False)
+    a, _, ws = heom.propagate(h, w["rho0"], 1.0, 320, record_every=64, precision=precision)
+    b, s_b, _ = heom.propagate(h, None, 1.0, 320, record_every=64, precision=precision,
+                               workspace=ws, resume=True)
+    assert np.array_equal(a, ref[:6]) and np.array_equal(b[1:], ref[6:])
+    assert np.array_equal(s_b, s_ref)
+
+
+def _serving_requests(n, seed=0):
+    from paper_1012_4382_amd.serve import Request
+
+    reqs = []
+    for j, w in enumerate(workloads.serving_trace(n)):
+        # Short runs so the oracle can check them too.
+        steps = 150 + 37 * j
+        reqs.append(Request(id=j, system=w["system"], depth=min(w["depth"], 2 if w["system"]["H"].shape[0] >= 12 else 3),
+                            rho0=w["rho0"], steps=steps, arrival_s=0.0))
+    return reqs
+
+
+def test_slots_equal_single_solves_and_continue():
+    """heom_advance_slots over separate workspaces, started and continued in
+    chunks, equals heom_propagate on each run alone (bitwise)."""
+    import torch
+
+    _say("case: advance_slots (mixed N and depth) vs heom_propagate")
+    reqs = _serving_requests(5)
+    hs = [heom.Hierarchy(r.system, r.depth) for r in reqs]
+    wss = [heom.allocate_workspace(h.workspace_bytes[heom.HEOM_FP64]) for h in hs]
+    scratch = heom.allocate_workspace(heom.slots_scratch_bytes(hs))
+    rhos, sinks = heom.advance_slots(hs, wss, [True] * 5, [r.rho0 for r in reqs], 1.0, 70, scratch)
+    rhos, sinks = heom.advance_slots(hs, wss, [False] * 5, None, 1.0, 80, scratch)
+    torch.cuda.synchronize()
+    for k, (h, r) in enumerate(zip(hs, reqs)):
+        ref, s_ref, _ = heom.propagate(h, r.rho0, 1.0, 150, record_every=150)
+        assert np.array_equal(rhos[k], ref[-1]), k
+        assert np.array_equal(sinks[k], s_ref), k
+
+
+def test_served_results_equal_alone_and_oracle():
+    """Requests of different N and depth served together by the engine give
+    bitwise the results they give served alone, and match the oracle."""
+    from paper_1012_4382_amd.serve import Engine, GpuBackend
+
+    _say("case: serving engine, mix vs alone vs oracle")
+    mix = _serving_requests(6)
+    eng = Engine(GpuBackend(), hbm_budget_bytes=8 << 30, chunk_steps=64)
+    m = eng.run(mix)
+    assert m["completed"] == 6
+    assert max(eng.occupancy_sum, 0) > 0 and m["mean_occupancy"] > 1.0
+    for r in mix:
+        alone = _serving_requests(6)[r.id]
+        Engine(GpuBackend(), hbm_budget_bytes=8 << 30, chunk_steps=64).run([alone])
+        assert np.array_equal(alone.rho_final, r.rho_final), r.id
+        assert np.array_equal(alone.sinks, r.sinks), r.id
+        ref = oracle.propagate(r.system, r.depth, r.rho0, 1.0, r.steps, record_every=r.steps)
+        assert _rel(r.rho_final, ref["rho"][-1]) <= FP64_TOL
+        assert abs(r.sinks[0] - ref["scalars"][0]) <= FP64_TOL * max(ref["scalars"][0], 1e-300)

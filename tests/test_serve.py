@@ -1,0 +1,154 @@
+"""Serving engine logic on the CPU: admission by memory budget, continuous
+batching, cancellation, rejection, failure isolation and latency bookkeeping,
+with a virtual clock.  The device is replaced by a backend that advances each
+request with the FP64 oracle (so results can be checked) and charges virtual
+time for the work."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1012_4382_amd import workloads
+from paper_1012_4382_amd.serve import Engine, Request
+
+
+class VClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(0.0, dt)
+
+
+class OracleBackend:
+    """Engine backend on the oracle; 1 ns of virtual time per ADO-step."""
+
+    def __init__(self, clock, fail_ids=(), bytes_per_ado=1000):
+        self.clock = clock
+        self.fail_ids = set(fail_ids)
+        self.bytes_per_ado = bytes_per_ado
+        self.calls = []  # ids advanced together, per call
+
+    def footprint(self, req):
+        n, _ = oracle.count(req.system, req.depth)
+        return n * self.bytes_per_ado, n
+
+    def admit(self, req, n):
+        req.n_ados = n
+        return {"state": None, "n": n}
+
+    def advance(self, reqs, slots, k):
+        self.calls.append([r.id for r in reqs])
+        if any(r.id in self.fail_ids for r in reqs):
+            raise RuntimeError("device fault in a request")
+        rhos, sinks = [], np.zeros((len(reqs), 3))
+        for i, (r, s) in enumerate(zip(reqs, slots)):
+            out = oracle.propagate(r.system, r.depth, r.rho0, r.dt, k, record_every=max(k, 1),
+                                   want_state=True, state_in=s["state"], n_threads=1)
+            s["state"] = out["state"]
+            rhos.append(out["rho"][-1])
+            sinks[i] = out["scalars"]
+        self.clock.t += k * sum(s["n"] for s in slots) * 1e-9
+        return rhos, sinks
+
+    def release(self, slot):
+        slot["state"] = None
+
+
+def _req(i, arrival, steps=120, depth=2, N=2):
+    rng = np.random.default_rng(i)
+    H = np.diag(rng.normal(12400, 100, N))
+    for a in range(N - 1):
+        H[a, a + 1] = H[a + 1, a] = rng.normal(-80, 20)
+    trap = np.zeros(N)
+    trap[-1] = 1.0
+    return Request(id=i, system=workloads.system(H, trap=trap, rec=np.full(N, 1e-3)),
+                   depth=depth, rho0=workloads.site_state(N, 1), steps=steps, arrival_s=arrival)
+
+
+def test_results_match_the_request_run_alone():
+    """Chunked, batched service gives bitwise the oracle's straight run."""
+    clock = VClock()
+    eng = Engine(OracleBackend(clock), hbm_budget_bytes=10**9, chunk_steps=50, clock=clock,
+                 sleep=clock.sleep)
+    reqs = [_req(i, arrival=i * 1e-7, steps=60 + 37 * i, depth=2 + i % 2, N=2 + i % 3)
+            for i in range(5)]
+    m = eng.run(reqs)
+    assert m["completed"] == 5
+    for r in reqs:
+        ref = oracle.propagate(r.system, r.depth, r.rho0, r.dt, r.steps, record_every=r.steps,
+                               n_threads=1)
+        assert np.array_equal(r.rho_final, ref["rho"][-1]), r.id
+        assert np.array_equal(r.sinks, ref["scalars"]), r.id
+
+
+def test_admission_respects_budget_and_fifo():
+    clock = VClock()
+    be = OracleBackend(clock, bytes_per_ado=1000)
+    # Depth 2 dimer: 6 ADOs -> 6000 bytes each; budget fits two at a time.
+    eng = Engine(be, hbm_budget_bytes=13000, chunk_steps=40, clock=clock, sleep=clock.sleep)
+    reqs = [_req(i, arrival=0.0, steps=80) for i in range(5)]
+    m = eng.run(reqs)
+    assert m["completed"] == 5
+    assert max(len(c) for c in be.calls) == 2
+    admits = [r.admit_s for r in sorted(reqs, key=lambda r: r.id)]
+    assert admits == sorted(admits)  # first come, first served
+    assert eng.in_use == 0
+
+
+def test_continuous_batching_admits_while_others_run():
+    clock = VClock()
+    be = OracleBackend(clock)
+    eng = Engine(be, hbm_budget_bytes=10**9, chunk_steps=10, clock=clock, sleep=clock.sleep)
+    long = _req(0, arrival=0.0, steps=400)
+    late = _req(1, arrival=0.5e-6, steps=40)   # arrives while `long` is running
+    m = eng.run([long, late])
+    assert m["completed"] == 2
+    assert any(set(c) == {0, 1} for c in be.calls)  # they shared launches
+    assert late.finish_s < long.finish_s
+    assert late.admit_s < long.finish_s
+
+
+def test_rejection_cancellation_and_failure_isolation():
+    clock = VClock()
+    be = OracleBackend(clock, fail_ids={2})
+    eng = Engine(be, hbm_budget_bytes=20000, chunk_steps=20, clock=clock, sleep=clock.sleep)
+    big = _req(9, arrival=0.0, depth=6, N=3)      # 84 ADOs -> 84000 bytes > budget
+    reqs = [_req(i, arrival=0.0, steps=60) for i in range(4)] + [big]
+    for r in reqs:
+        eng.submit(r)
+    assert big.status == "rejected" and "budget" in big.error
+    assert eng.cancel(3) and reqs[3].status == "cancelled"
+    while eng.step():
+        pass
+    assert reqs[2].status == "failed" and "device fault" in reqs[2].error
+    assert reqs[0].status == reqs[1].status == "done"
+    ref = oracle.propagate(reqs[0].system, 2, reqs[0].rho0, 1.0, 60, record_every=60, n_threads=1)
+    assert np.array_equal(reqs[0].sinks, ref["scalars"])
+    assert eng.in_use == 0
+    m = eng.metrics()
+    assert (m["completed"], m["failed"], m["rejected"], m["cancelled"]) == (2, 1, 1, 1)
+
+
+def test_latency_bookkeeping_with_virtual_clock():
+    clock = VClock()
+    eng = Engine(OracleBackend(clock), hbm_budget_bytes=10**9, chunk_steps=100, clock=clock,
+                 sleep=clock.sleep)
+    reqs = [_req(i, arrival=1.0 + i, steps=100) for i in range(3)]  # well separated
+    m = eng.run(reqs)
+    for r in reqs:
+        # Alone on the device: latency = its own work, 6 ADOs x 100 steps x 1 ns.
+        assert r.latency_s == pytest.approx(600e-9, rel=1e-6)
+    assert m["p50_latency_s"] == pytest.approx(600e-9, rel=1e-6)
+    assert math.isclose(m["mean_occupancy"], 1.0)
+
+
+def test_engine_argument_validation():
+    with pytest.raises(ValueError):
+        Engine(OracleBackend(VClock()), hbm_budget_bytes=0)
+    with pytest.raises(ValueError):
+        Engine(OracleBackend(VClock()), hbm_budget_bytes=10, chunk_steps=0)
