@@ -24,7 +24,7 @@ namespace heom {
 
 // stage_kernels.hip
 bool has_fixed_kernel(int N, int KP);
-int tile_threads(int N);
+int tile_threads(int N, bool mixed);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
                         const WorkItem *work, int n_items, int block, int stage, double coef,
                         int hist_slot, hipStream_t stream);
@@ -91,7 +91,8 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   // Work items: stage items (at most one per 64 ADOs) and initialisation
   // items (one per 64 ADOs).
   int64_t cap = 0;
-  for (int k = 0; k < n; ++k) cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad);
+  // (+8 per instance: padding of a kernel group to a multiple of the XCD count)
+  for (int k = 0; k < n; ++k) cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad) + 8;
   L.work = off;
   L.work_cap = cap;
   off = align_up(off + sizeof(WorkItem) * cap);
@@ -205,6 +206,19 @@ void unpack_hermitian(int N, const double *packed, double *rho) {
 
 // Steps captured in one graph.
 constexpr int64_t kGraphSteps = 32;
+
+// MI355X has 8 XCDs, each with its own L2; workgroups are dispatched to them
+// round-robin by workgroup index.
+constexpr int64_t kXcds = 8;
+
+// XCD-aware ordering of the work list (HEOM_XCD_REMAP=0 turns it off).
+bool xcd_remap() {
+  static bool v = [] {
+    const char *s = std::getenv("HEOM_XCD_REMAP");
+    return !(s && s[0] == '0');
+  }();
+  return v;
+}
 
 // A private stream per device and host thread, used only to capture graphs
 // (capture on the caller's stream is not possible when it is the legacy
@@ -366,15 +380,30 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     g.KP = std::get<2>(kv.first);
     if (g.kind == KernelKind::kTile) {
       g.ados_per_item = 64;
-      g.threads = tile_threads(g.N);
+      g.threads = tile_threads(g.N, mixed);
     } else {
       g.ados_per_item = block_ados();
       g.threads = g.ados_per_item;
     }
     g.item_begin = static_cast<int64_t>(items.size());
+    std::vector<WorkItem> mine;
     for (int k : kv.second)
       for (int64_t first = 0; first < hs[k]->n_ados; first += g.ados_per_item)
-        items.push_back({k, static_cast<int32_t>(first)});
+        mine.push_back({k, static_cast<int32_t>(first)});
+    if (xcd_remap()) {
+      // Workgroup b runs on XCD b % kXcds.  Give XCD x the x-th contiguous
+      // eighth of the list (consecutive tiles of the same instance), so that
+      // neighbour gathers hit the L2 of the XCD that staged their tiles.
+      // Padding items start past the instance's last ADO and exit at once.
+      const int64_t len = (static_cast<int64_t>(mine.size()) + kXcds - 1) / kXcds;
+      const WorkItem pad = {mine.back().inst, static_cast<int32_t>(hs[mine.back().inst]->n_ados)};
+      mine.resize(len * kXcds, pad);
+      std::vector<WorkItem> perm(mine.size());
+      for (int64_t b = 0; b < static_cast<int64_t>(perm.size()); ++b)
+        perm[b] = mine[(b % kXcds) * len + b / kXcds];
+      mine.swap(perm);
+    }
+    items.insert(items.end(), mine.begin(), mine.end());
     g.n_items = static_cast<int64_t>(items.size()) - g.item_begin;
     groups.push_back(g);
   }
@@ -560,7 +589,7 @@ SlotScratch slot_scratch(heom_hierarchy *const *hs, int n) {
   SlotScratch s;
   s.descs = 0;
   size_t off = align_up(sizeof(InstDesc) * n);
-  for (int k = 0; k < n; ++k) s.work_cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad);
+  for (int k = 0; k < n; ++k) s.work_cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad) + 8;
   s.work = off;
   s.total = align_up(off + sizeof(WorkItem) * s.work_cap);
   return s;

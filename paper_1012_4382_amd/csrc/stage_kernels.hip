@@ -351,14 +351,20 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
   const ParamOffsets o = param_offsets(N, M);
   const StageBufs bufs = stage_bufs(d, stage);
   const int64_t S = d.stride;
-  const T *__restrict__ X = static_cast<const T *>(bufs.x);
-  const T *__restrict__ Yp = static_cast<const T *>(bufs.y);
-  T *__restrict__ Out = static_cast<T *>(bufs.out);
-  const double *__restrict__ P = d.params;
+  const HEOM_GLOBAL T *X = gmem(static_cast<const T *>(bufs.x));
+  const HEOM_GLOBAL T *Yp = gmem(static_cast<const T *>(bufs.y));
+  HEOM_GLOBAL T *Out = gmem(static_cast<T *>(bufs.out));
+  const HEOM_CONST double *P = cmem(d.params);
+  const HEOM_GLOBAL int32_t *up = gmem(d.up);
+  const HEOM_GLOBAL int32_t *down = gmem(d.down);
+  const HEOM_GLOBAL uint8_t *occ = gmem(d.occ);
+  const HEOM_GLOBAL double *x0 = gmem(bufs.x0);
+  const HEOM_GLOBAL double *y0 = gmem(bufs.y0);
+  HEOM_GLOBAL double *out0 = gmem(bufs.out0);
   const C coef = static_cast<C>(coef_d);
 
   auto ld = [&](int e) -> C {  // own stage input, packed element e
-    if constexpr (MIXED && IS0) return bufs.x0[e];
+    if constexpr (MIXED && IS0) return x0[e];
     return static_cast<C>(X[e * S + i]);
   };
   auto elem = [&](int c, int b) -> Cx<C> {
@@ -372,7 +378,7 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
   };
   C damp = C(0);
   for (int m = 0; m < M; ++m)
-    damp += static_cast<C>(d.occ[m * S + i]) * static_cast<C>(P[o.nu + m]);
+    damp += static_cast<C>(occ[m * S + i]) * static_cast<C>(P[o.nu + m]);
 
   for (int a = 0; a < N; ++a) {
     for (int b = a; b < N; ++b) {
@@ -399,20 +405,20 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
         const int ma = a * KP + k;
         const int mb = b * KP + k;
         if (a != b) {
-          const int ja = d.up[ma * S + i];
+          const int ja = up[ma * S + i];
           if (ja >= 0) {
             ar -= static_cast<C>(X[(e + 1) * S + ja]);
             ai += static_cast<C>(X[e * S + ja]);
           }
-          const int jb = d.up[mb * S + i];
+          const int jb = up[mb * S + i];
           if (jb >= 0) {
             ar += static_cast<C>(X[(e + 1) * S + jb]);
             ai -= static_cast<C>(X[e * S + jb]);
           }
         }
-        const int ja = d.down[ma * S + i];
+        const int ja = down[ma * S + i];
         if (ja >= 0) {
-          const C n = static_cast<C>(d.occ[ma * S + i]);
+          const C n = static_cast<C>(occ[ma * S + i]);
           const C vr = static_cast<C>(X[e * S + ja]);
           const C vi = (a == b) ? C(0) : static_cast<C>(X[(e + 1) * S + ja]);
           const C cr = n * static_cast<C>(P[o.c_re + ma]);
@@ -420,9 +426,9 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
           ar -= ci * vr + cr * vi;
           ai += cr * vr - ci * vi;
         }
-        const int jb = d.down[mb * S + i];
+        const int jb = down[mb * S + i];
         if (jb >= 0) {
-          const C n = static_cast<C>(d.occ[mb * S + i]);
+          const C n = static_cast<C>(occ[mb * S + i]);
           const C vr = static_cast<C>(X[e * S + jb]);
           const C vi = (a == b) ? C(0) : static_cast<C>(X[(e + 1) * S + jb]);
           const C cr = n * static_cast<C>(P[o.c_re + mb]);
@@ -444,12 +450,11 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
       }
       const C nr = yr + coef * ar;
       const C ni = yi + coef * ai;
-      // The stage input is still read below (elem) by this lane only after all
-      // of its own writes: the last stage writes y in place, but y is never the
-      // stage input of the last stage, so the reads above stay valid.
+      // The last stage writes y in place; y is never the stage input of the
+      // last stage, so the stage-input reads of later elements stay valid.
       if constexpr (MIXED && IS0) {
-        bufs.out0[e] = nr;
-        if (a != b) bufs.out0[e + 1] = ni;
+        out0[e] = nr;
+        if (a != b) out0[e + 1] = ni;
       }
       Out[e * S + i] = static_cast<T>(nr);
       if (a != b) Out[(e + 1) * S + i] = static_cast<T>(ni);
@@ -539,19 +544,32 @@ __host__ __device__ constexpr int ent_im(int N, int r, int c) {
 __host__ __device__ constexpr int ent_sg(int r, int c) { return r > c ? -1 : 1; }
 
 // Target packed elements per wave of the tile kernel, and how many of a
-// wave's elements have their global loads in flight together (one chunk).
-#ifndef HEOM_TILE_ELEMS_PER_WAVE
-#define HEOM_TILE_ELEMS_PER_WAVE 4
+// wave's elements have their global loads in flight together (one chunk), for
+// FP64 and FP32 storage.  Measured on the FMO-shaped 7-site workloads: FP64
+// does best with fewer, longer waves (so that all workgroups are resident at
+// its register use) and short load chunks; FP32 with more waves and longer
+// chunks.  Each can be overridden at build time.
+#ifndef HEOM_TILE_ELEMS_PER_WAVE_F64
+#define HEOM_TILE_ELEMS_PER_WAVE_F64 7
 #endif
-#ifndef HEOM_TILE_CHUNK
-#define HEOM_TILE_CHUNK 4
+#ifndef HEOM_TILE_CHUNK_F64
+#define HEOM_TILE_CHUNK_F64 2
+#endif
+#ifndef HEOM_TILE_ELEMS_PER_WAVE_F32
+#define HEOM_TILE_ELEMS_PER_WAVE_F32 4
+#endif
+#ifndef HEOM_TILE_CHUNK_F32
+#define HEOM_TILE_CHUNK_F32 4
+#endif
+#ifndef HEOM_TILE_CHUNK_BARRIER
+#define HEOM_TILE_CHUNK_BARRIER 1
 #endif
 
 // Waves per tile workgroup: the divisor of the N(N+1)/2 packed elements
-// (at most 16) that gives closest to HEOM_TILE_ELEMS_PER_WAVE elements per wave.
-__host__ __device__ constexpr int tile_waves_for(int N) {
+// (at most 16) that gives closest to the target elements per wave.
+__host__ __device__ constexpr int tile_waves_for(int N, bool fp64) {
   const int P = N * (N + 1) / 2;
-  const int t = HEOM_TILE_ELEMS_PER_WAVE;
+  const int t = fp64 ? HEOM_TILE_ELEMS_PER_WAVE_F64 : HEOM_TILE_ELEMS_PER_WAVE_F32;
   int best = 1;
   for (int w = 1; w <= 16 && w <= P; ++w) {
     if (P % w) continue;
@@ -726,10 +744,19 @@ template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool X0S
 __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int P = N * (N + 1) / 2;
   constexpr int count = (P - G + W - 1) / W;
-  constexpr int CH = HEOM_TILE_CHUNK;
+  // An element gathers 4 neighbours per mode of its sites: with more modes
+  // per site, fewer elements per chunk keep the loaded values in registers.
+  constexpr int CH0 = sizeof(T) == 8 ? HEOM_TILE_CHUNK_F64 : HEOM_TILE_CHUNK_F32;
+  constexpr int CH = CH0 / KP > 0 ? CH0 / KP : 1;
   if constexpr (OFF < count) {
     constexpr int len = (count - OFF < CH) ? count - OFF : CH;
     tile_chunk<N, KP, G, W, OFF, C, T, X0SRC>(c, std::make_integer_sequence<int, len>{});
+    // Keep the next chunk's LDS reads from being hoisted above this chunk
+    // (they cannot alias its global stores), which would hold every operand
+    // of the wave's elements in registers at once.
+#if HEOM_TILE_CHUNK_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
     tile_chunks<N, KP, G, W, OFF + CH, C, T, X0SRC>(c);
   }
 }
@@ -746,12 +773,13 @@ __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
 }
 
 template <int N, int KP, typename T>
-__global__ void __launch_bounds__(64 * tile_waves_for(N), HEOM_TILE_MIN_WAVES_PER_SIMD)
+__global__ void __launch_bounds__(64 * tile_waves_for(N, sizeof(T) == 8),
+                                  HEOM_TILE_MIN_WAVES_PER_SIMD)
     stage_tile(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
                double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
   constexpr int N2 = N * N;
   constexpr int M = N * KP;
-  constexpr int W = tile_waves_for(N);
+  constexpr int W = tile_waves_for(N, sizeof(T) == 8);
   constexpr bool MIXED = sizeof(T) == 4;
   __shared__ T sx[(N2 + 1) * kTile];
   __shared__ int32_t sup[M * kTile];
@@ -916,7 +944,7 @@ static StageKernel tile_kernel(int N, int KP) {
 
 bool has_fixed_kernel(int N, int KP) { return lane_kernel<double>(N, KP) != nullptr; }
 
-int tile_threads(int N) { return 64 * tile_waves_for(N); }
+int tile_threads(int N, bool mixed) { return 64 * tile_waves_for(N, !mixed); }
 
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
                         const WorkItem *work, int n_items, int block, int stage, double coef,
