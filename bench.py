@@ -38,7 +38,68 @@ def _parse():
                    help="skip the HBM-resident N=7, depth-16 measurement")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 256 MiB device copy (reference for traffic counters)")
+    p.add_argument("--no-sweep", action="store_true",
+                   help="skip the 64-instance parameter-sweep measurement")
+    p.add_argument("--serve", type=int, default=0, metavar="R",
+                   help="also serve the first R requests of the serving trace (0: skip)")
     return p.parse_args()
+
+
+def _sweep(heom, torch, workloads, stream):
+    """64 uneven parameter-sweep instances (one Matsubara term per bath, depth
+    3-5), 1000 RK4 steps: one batched launch sequence vs one instance at a time."""
+    ws_ = [workloads.sweep_instance(i) for i in range(64)]
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in ws_]
+    r0 = [w["rho0"] for w in ws_]
+    steps = ws_[0]["steps"]
+    total = sum(h.n_ados for h in hs) * steps
+    out = {"instances": len(hs), "ados_min": min(h.n_ados for h in hs),
+           "ados_max": max(h.n_ados for h in hs), "rk4_steps": steps}
+    for prec in ("fp64", "fp32"):
+        ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, prec))
+        heom.propagate_batch(hs, r0, 1.0, 50, record_every=50, precision=prec, workspace=ws,
+                             stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        heom.propagate_batch(hs, r0, 1.0, steps, record_every=steps, precision=prec, workspace=ws,
+                             stream=stream)
+        torch.cuda.synchronize()
+        out[f"{prec}_batched_ado_steps_per_s"] = total / (time.perf_counter() - t0)
+    wsb = heom.allocate_workspace(max(h.workspace_bytes[heom.HEOM_FP64] for h in hs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h, r in zip(hs, r0):
+        heom.propagate(h, r, 1.0, steps, record_every=steps, workspace=wsb, stream=stream)
+    torch.cuda.synchronize()
+    out["fp64_one_at_a_time_ado_steps_per_s"] = total / (time.perf_counter() - t0)
+    out["fp64_batched_over_one_at_a_time"] = (out["fp64_batched_ado_steps_per_s"] /
+                                             out["fp64_one_at_a_time_ado_steps_per_s"])
+    return out
+
+
+def _serve(heom, workloads, stream, n_requests):
+    """The first n_requests of the serving trace (Poisson arrivals, mean 50 ms;
+    N in {2,7,8,12,24}, depth 2-4, 2-10 ps), served by the continuous-batching
+    engine in real time, then the same requests one at a time (FIFO)."""
+    from paper_1012_4382_amd.serve import Engine, GpuBackend, Request
+
+    def reqs():
+        return [Request(id=w["id"], system=w["system"], depth=w["depth"], rho0=w["rho0"],
+                        steps=w["steps"], arrival_s=w["arrival_s"])
+                for w in workloads.serving_trace(n_requests)]
+
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.9)
+    eng = Engine(GpuBackend(stream=stream), hbm_budget_bytes=budget, chunk_steps=200)
+    m = eng.run(reqs())
+    fifo = Engine(GpuBackend(stream=stream), hbm_budget_bytes=budget, chunk_steps=200)
+    fifo_reqs = reqs()
+    # One at a time: admission budget of one request's footprint.
+    fifo.budget = max(fifo.backend.footprint(r)[0] for r in fifo_reqs)
+    mf = fifo.run(fifo_reqs)
+    return {"requests": n_requests, "budget_bytes": budget, "continuous_batching": m,
+            "fifo_one_at_a_time": mf}
 
 
 def _stage_kernel_timing(heom, torch, hs, rho0s, stream, kernel, precision="fp64", steps=500):
@@ -191,6 +252,10 @@ def main():
                               "fp64_batched_over_single": value / plain}
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
+    if not args.no_sweep:
+        result["sweep"] = _sweep(heom, torch, workloads, stream)
+    if args.serve > 0:
+        result["serving"] = _serve(heom, workloads, stream, args.serve)
     if args.copy_calibration:
         # A plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
         # kernel calibrate the traffic counters of the stage kernel.

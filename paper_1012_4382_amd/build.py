@@ -24,7 +24,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
-SOURCES = ["params.cpp", "hierarchy.cpp", "runtime.cpp", "stage_kernels.hip"]
+SOURCES = ["params.cpp", "hierarchy.cpp", "runtime.cpp", "kernels_dispatch.hip",
+           "kernels_lane.hip", "kernels_tile_small.hip", "kernels_tile_7.hip",
+           "kernels_tile_8.hip", "kernels_tile_9_10.hip", "kernels_tile_11.hip",
+           "kernels_tile_12.hip"]
+# The largest translation units first, so the parallel build ends sooner.
+_ORDER = ["kernels_tile_12.hip", "kernels_tile_11.hip", "kernels_tile_9_10.hip",
+          "kernels_tile_8.hip", "kernels_tile_7.hip"]
 
 
 def _compile(src: str, defines=(), build_dir: str = BUILD_DIR) -> str:
@@ -44,8 +50,10 @@ def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BU
     `defines` are extra preprocessor definitions (tuning knobs of the kernels).
     """
     os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda src: _compile(src, defines, build_dir), SOURCES))
+    order = _ORDER + [s for s in SOURCES if s not in _ORDER]
+    workers = max(1, min(len(order), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda src: _compile(src, defines, build_dir), order))
     tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -94,6 +94,10 @@ struct WorkItem {
   int32_t first;
 };
 
+// Host-side handle of a stage kernel: (descriptors, work list, stage index,
+// stage coefficient dt/4, dt/3, dt/2 or dt, history slot or -1).
+typedef void (*StageKernel)(const InstDesc *, const WorkItem *, int, double, int);
+
 }  // namespace heom
 
 // Host-side hierarchy handle.

@@ -1,0 +1,35 @@
+// kernels_tile_small.hip -- instances of the tile stage kernel for
+// N=1 K+1=1, N=2 K+1=1, N=3 K+1=1, N=4 K+1=1, N=5 K+1=1, N=6 K+1=1, N=1 K+1=2, N=2 K+1=2, N=3 K+1=2, N=4 K+1=2, N=5 K+1=2, N=6 K+1=2 (FP64 and FP32-mixed storage).
+#include "stage_kernels.h"
+
+namespace heom {
+
+StageKernel tile_kernel_part_small(int N, int KP, bool mixed) {
+  if (N == 1 && KP == 1)
+    return mixed ? &stage_tile<1, 1, float> : &stage_tile<1, 1, double>;
+  if (N == 2 && KP == 1)
+    return mixed ? &stage_tile<2, 1, float> : &stage_tile<2, 1, double>;
+  if (N == 3 && KP == 1)
+    return mixed ? &stage_tile<3, 1, float> : &stage_tile<3, 1, double>;
+  if (N == 4 && KP == 1)
+    return mixed ? &stage_tile<4, 1, float> : &stage_tile<4, 1, double>;
+  if (N == 5 && KP == 1)
+    return mixed ? &stage_tile<5, 1, float> : &stage_tile<5, 1, double>;
+  if (N == 6 && KP == 1)
+    return mixed ? &stage_tile<6, 1, float> : &stage_tile<6, 1, double>;
+  if (N == 1 && KP == 2)
+    return mixed ? &stage_tile<1, 2, float> : &stage_tile<1, 2, double>;
+  if (N == 2 && KP == 2)
+    return mixed ? &stage_tile<2, 2, float> : &stage_tile<2, 2, double>;
+  if (N == 3 && KP == 2)
+    return mixed ? &stage_tile<3, 2, float> : &stage_tile<3, 2, double>;
+  if (N == 4 && KP == 2)
+    return mixed ? &stage_tile<4, 2, float> : &stage_tile<4, 2, double>;
+  if (N == 5 && KP == 2)
+    return mixed ? &stage_tile<5, 2, float> : &stage_tile<5, 2, double>;
+  if (N == 6 && KP == 2)
+    return mixed ? &stage_tile<6, 2, float> : &stage_tile<6, 2, double>;
+  return nullptr;
+}
+
+}  // namespace heom

@@ -24,6 +24,7 @@ namespace heom {
 
 // stage_kernels.hip
 bool has_fixed_kernel(int N, int KP);
+bool has_tile_kernel(int N, int KP);
 int tile_threads(int N, bool mixed);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
                         const WorkItem *work, int n_items, int block, int stage, double coef,
@@ -366,8 +367,13 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   for (int k = 0; k < n; ++k) {
     const heom_hierarchy *h = hs[k];
     KernelKind kind = KernelKind::kGeneric;
-    if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real && has_fixed_kernel(h->N, h->KP))
-      kind = (flags & HEOM_LANE_KERNEL) ? KernelKind::kLane : KernelKind::kTile;
+    if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real) {
+      if (flags & HEOM_LANE_KERNEL) {
+        if (has_fixed_kernel(h->N, h->KP)) kind = KernelKind::kLane;
+      } else if (has_tile_kernel(h->N, h->KP)) {
+        kind = KernelKind::kTile;
+      }
+    }
     const int kp = (kind == KernelKind::kGeneric) ? 0 : h->KP;
     by_key[std::make_tuple(static_cast<int>(kind), h->N, kp)].push_back(k);
   }

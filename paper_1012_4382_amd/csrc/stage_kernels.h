@@ -1,4 +1,7 @@
-// stage_kernels.hip -- fused RK4-stage kernels of the HEOM propagation (gfx950).
+// stage_kernels.h -- device code of the fused RK4-stage kernels (gfx950),
+// included by the kernels_*.hip translation units, which instantiate and
+// launch them (split so that the build compiles them in parallel).
+//
 //
 // One launch evaluates the right-hand side of eq:lab8 (paper, Appendix A) for
 // every ADO of a set of instances and applies one RK4 stage to it.
@@ -41,6 +44,8 @@
 //    and H, c, nu are wave-uniform scalar loads.
 //  * stage_generic: any N <= 64, any K, complex H; reads the stage input
 //    straight from the planes (all such reads are coalesced across lanes).
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -913,75 +918,5 @@ __global__ void snapshot(const InstDesc *__restrict__ descs, int n_inst, int slo
 }
 
 }  // namespace
-
-// ---------------------------------------------------------------------------
-// Launch entry points used by the host runtime.
-// ---------------------------------------------------------------------------
-
-typedef void (*StageKernel)(const InstDesc *, const WorkItem *, int, double, int);
-
-#define HEOM_FOR_EACH_FIXED(X) \
-  X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) \
-  X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2)
-
-template <typename T>
-static StageKernel lane_kernel(int N, int KP) {
-#define HEOM_CASE(n, kp) \
-  if (N == n && KP == kp) return &stage_fixed<n, kp, T>;
-  HEOM_FOR_EACH_FIXED(HEOM_CASE)
-#undef HEOM_CASE
-  return nullptr;
-}
-
-template <typename T>
-static StageKernel tile_kernel(int N, int KP) {
-#define HEOM_CASE(n, kp) \
-  if (N == n && KP == kp) return &stage_tile<n, kp, T>;
-  HEOM_FOR_EACH_FIXED(HEOM_CASE)
-#undef HEOM_CASE
-  return nullptr;
-}
-
-bool has_fixed_kernel(int N, int KP) { return lane_kernel<double>(N, KP) != nullptr; }
-
-int tile_threads(int N, bool mixed) { return 64 * tile_waves_for(N, !mixed); }
-
-hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
-                        const WorkItem *work, int n_items, int block, int stage, double coef,
-                        int hist_slot, hipStream_t stream) {
-  StageKernel k = nullptr;
-  switch (kind) {
-    case KernelKind::kTile:
-      k = mixed ? tile_kernel<float>(N, KP) : tile_kernel<double>(N, KP);
-      break;
-    case KernelKind::kLane:
-      k = mixed ? lane_kernel<float>(N, KP) : lane_kernel<double>(N, KP);
-      break;
-    case KernelKind::kGeneric:
-      k = mixed ? &stage_generic<float> : &stage_generic<double>;
-      break;
-  }
-  if (!k) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(n_items), dim3(block), 0, stream, descs, work, stage, coef, hist_slot);
-  return hipGetLastError();
-}
-
-hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
-                       int block, hipStream_t stream) {
-  if (mixed)
-    hipLaunchKernelGGL(init_state<float>, dim3(n_items), dim3(block), 0, stream, descs, work);
-  else
-    hipLaunchKernelGGL(init_state<double>, dim3(n_items), dim3(block), 0, stream, descs, work);
-  return hipGetLastError();
-}
-
-hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
-                           hipStream_t stream) {
-  if (mixed)
-    hipLaunchKernelGGL(snapshot<float>, dim3(n_inst), dim3(64), 0, stream, descs, n_inst, slot);
-  else
-    hipLaunchKernelGGL(snapshot<double>, dim3(n_inst), dim3(64), 0, stream, descs, n_inst, slot);
-  return hipGetLastError();
-}
 
 }  // namespace heom

@@ -143,9 +143,12 @@ def test_complex_hamiltonian_generic_kernel():
     assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("kernel", ["auto", "generic"])
 @pytest.mark.parametrize("N,depth,steps", [(12, 2, 400), (24, 1, 300), (9, 2, 300)])
-def test_generic_kernel_larger_sites(N, depth, steps):
-    """Chains of the serving workload's sizes through the generic kernel."""
+def test_larger_sites(N, depth, steps, kernel, precision):
+    """Chains of the serving workload's sizes: the tile kernel (up to 12 sites)
+    and the generic kernel, FP64 and FP32-mixed."""
     rng = np.random.default_rng(N)
     H = np.diag(rng.normal(12400, 100, N))
     for i in range(N - 1):
@@ -154,11 +157,25 @@ def test_generic_kernel_larger_sites(N, depth, steps):
     trap[-1] = 1.0
     sys = workloads.system(H, trap=trap, rec=np.full(N, 1e-3))
     rho0 = workloads.site_state(N, 1)
-    _say(f"case: chain N={N} D={depth} {steps} steps")
+    _say(f"case: chain N={N} D={depth} {steps} steps kernel={kernel} {precision}")
     h = heom.Hierarchy(sys, depth)
-    rho, sinks, _ = heom.propagate(h, rho0, 1.0, steps, record_every=10)
-    ref = oracle.propagate(sys, depth, rho0, 1.0, steps, record_every=10)
-    assert _rel(rho, ref["rho"]) <= FP64_TOL
+    rho, sinks, _ = heom.propagate(h, rho0, 1.0, steps, record_every=10, kernel=kernel,
+                                   precision=precision)
+    key = (N, depth, steps)
+    if key not in _CHAIN_REF:
+        _CHAIN_REF[key] = oracle.propagate(sys, depth, rho0, 1.0, steps, record_every=10)
+    ref = _CHAIN_REF[key]
+    if precision == "fp64":
+        assert _rel(rho, ref["rho"]) <= FP64_TOL
+        assert abs(sinks[0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0])
+    else:
+        p = np.real(np.diagonal(rho, axis1=1, axis2=2))
+        pr = np.real(np.diagonal(ref["rho"], axis1=1, axis2=2))
+        assert np.max(np.abs(p - pr)) <= FP32_TOL
+        assert abs(sinks[0] - ref["scalars"][0]) <= FP32_TOL
+
+
+_CHAIN_REF = {}
 
 
 # --- FP32 mixed precision ----------------------------------------------------------
