@@ -77,6 +77,30 @@ def _sweep(heom, torch, workloads, stream):
     return out
 
 
+def _precision(heom, workloads, stream):
+    """Precision workload: depth 8 (6435 ADOs), seeds 0-1, T = 77 and 300 K,
+    excitation at site 1, 5 ps.  Reports the FP32-mixed path's deviation from
+    the FP64 path (itself checked against the FP64 oracle to 1e-10 by the
+    tests): max |dp| over all populations and steps, and |d eta|."""
+    cases = [workloads.fmo_like(seed=s, site=1, depth=8, T=T) for s in (0, 1) for T in (77.0, 300.0)]
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in cases]
+    r0 = [w["rho0"] for w in cases]
+    steps = cases[0]["steps"]
+    res = {}
+    for prec in ("fp64", "fp32"):
+        rhos, sinks, _ = heom.propagate_batch(hs, r0, 1.0, steps, record_every=10, precision=prec,
+                                              stream=stream)
+        res[prec] = (rhos, sinks)
+    dp = max(float(np.max(np.abs(np.real(np.diagonal(a, axis1=1, axis2=2)) -
+                                 np.real(np.diagonal(b, axis1=1, axis2=2)))))
+             for a, b in zip(res["fp32"][0], res["fp64"][0]))
+    ptrap = res["fp64"][1][:, 0]
+    dtrap = np.abs(res["fp32"][1][:, 0] - ptrap)
+    return {"workload": "fmo_like_7site_depth8_T77_300_seeds01_5ps", "n_ados": hs[0].n_ados,
+            "max_abs_pop_error": dp, "max_abs_p_trap_error": float(np.max(dtrap)),
+            "max_rel_p_trap_error": float(np.max(dtrap / ptrap)), "bar": 1e-5}
+
+
 def _serve(heom, workloads, stream, n_requests):
     """The first n_requests of the serving trace (Poisson arrivals, mean 50 ms;
     N in {2,7,8,12,24}, depth 2-4, 2-10 ps), served by the continuous-batching
@@ -205,6 +229,13 @@ def main():
     # (N*N reals) per step, 11/4 per stage on average.
     bytes_per_launch = total_ados * (11.0 / 4.0) * N * N * 8
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    # Launch shape the autotuner chose for this workload (during the warm-up).
+    n_tiles = sum((h.n_ados + 63) // 64 for h in hs)
+    shape, shape_us = heom.autotune_lookup(N, 1, n_tiles, "fp64")
+    autotune = {"tiles": n_tiles, "shape": shape,
+                "first_stage_us_per_shape": [round(float(u), 3) for u in shape_us],
+                "shapes": [heom.tile_shape_info(N, 1, "fp64", k)
+                           for k in range(heom.tile_shape_count())]}
 
     result = {
         "metric": "HEOM ADO-steps/s (FP64, FP32) vs plain; serving p50/p99 latency at ≤1e-5 error",
@@ -225,11 +256,12 @@ def main():
                    "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": {"auto": f"stage_tile<{N},1,double>",
+                     "kernel": {"auto": f"stage_tile<{N},1,double,{max(shape, 0)}>",
                                 "lane": f"stage_fixed<{N},1,double>",
                                 "generic": "stage_generic<double>"}[args.kernel],
                      "kernel_avg_us": kernel_ms * 1e3, "bytes_per_launch": bytes_per_launch},
         "population_defect": defect,
+        "autotune": autotune,
     }
     if not args.no_variants:
         # Plain single solve (one instance at a time) and FP32-mixed batch.
@@ -254,6 +286,8 @@ def main():
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
     if not args.no_sweep:
         result["sweep"] = _sweep(heom, torch, workloads, stream)
+    if not args.no_variants:
+        result["precision"] = _precision(heom, workloads, stream)
     if args.serve > 0:
         result["serving"] = _serve(heom, workloads, stream, args.serve)
     if args.copy_calibration:

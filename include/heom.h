@@ -61,9 +61,14 @@ enum {
                                where a specialised one exists                   */
   HEOM_LANE_KERNEL = 4,     /* diagnostic: use the one-lane-per-ADO specialised
                                kernel instead of the LDS-tiled one (N <= 8)     */
-  HEOM_NO_GRAPH = 8         /* diagnostic: launch every stage kernel directly
+  HEOM_NO_GRAPH = 8,        /* diagnostic: launch every stage kernel directly
                                instead of replaying captured graphs of steps    */
+  HEOM_NO_AUTOTUNE = 16     /* use tile launch shape 0 instead of the
+                               autotuned one                                    */
 };
+/* Flag bits that force tile launch shape s (0 <= s < heom_tile_shape_count())
+ * for every tile-kernel group of a call. */
+#define HEOM_TILE_SHAPE(s) (((((int)(s)) + 1) & 0xf) << 8)
 
 typedef struct heom_hierarchy heom_hierarchy; /* opaque, library-owned */
 
@@ -129,7 +134,9 @@ int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, d
 /* Propagates rho0 by n_steps RK4 steps of dt_fs on the current device.
  *   precision      HEOM_FP64 or HEOM_FP32_MIXED
  *   flags          HEOM_RESUME: continue the run held in d_workspace (rho0 is
- *                  then ignored and may be NULL); HEOM_GENERIC_KERNEL
+ *                  then ignored and may be NULL); HEOM_GENERIC_KERNEL,
+ *                  HEOM_LANE_KERNEL, HEOM_NO_GRAPH, HEOM_NO_AUTOTUNE,
+ *                  HEOM_TILE_SHAPE(s) (see the autotuner below)
  *   rho0           [N][N] complex Hermitian initial reduced density matrix;
  *                  every deeper ADO starts at zero (text after eq:lab8)
  *   record_every   >= 1; rho is recorded at step 0 and every record_every steps
@@ -173,7 +180,8 @@ int heom_slots_scratch_bytes(heom_hierarchy *const *hs, int32_t n, size_t *bytes
  *   start[i]            1: initialise run i from rho0s[i] (N*N complex
  *                       Hermitian); 0: continue the run held in its workspace
  *                       (as HEOM_RESUME; rho0s[i] may be NULL)
- *   flags               HEOM_GENERIC_KERNEL, HEOM_LANE_KERNEL, HEOM_NO_GRAPH
+ *   flags               HEOM_GENERIC_KERNEL, HEOM_LANE_KERNEL, HEOM_NO_GRAPH,
+ *                       HEOM_NO_AUTOTUNE, HEOM_TILE_SHAPE(s)
  *   d_scratch           at least heom_slots_scratch_bytes(hs, n) bytes, 256-byte
  *                       aligned; its contents are not needed after the call
  *   rho_out[i]          host N*N complex: sigma_0 after the last step, or NULL
@@ -204,6 +212,40 @@ int heom_efficiency(heom_hierarchy *h, int precision, const double *rho0, double
  * followed by 3 doubles {P_trap, P_recomb, Q}.  Synchronises hip_stream. */
 int heom_read_state(const heom_hierarchy *h, int precision, const void *d_workspace,
                     size_t workspace_bytes, void *hip_stream, double *state_out);
+
+/* Launch shapes of the tile stage kernel and their autotuner.
+ *
+ * The stage kernel for real H and N <= 12 stages 64 consecutive ADOs per
+ * workgroup in LDS (the paper's blocking of ADOs per thread block, Appendix B,
+ * redone for wave64 and LDS).  It is built in several launch shapes, which
+ * differ in the waves per workgroup, the packed elements each wave computes
+ * and how many elements have their neighbour gathers in flight together;
+ * every shape performs the same arithmetic, so results do not depend on the
+ * shape.  Unless a call passes HEOM_NO_AUTOTUNE or HEOM_TILE_SHAPE(s), the
+ * first call that meets a new key (GPU architecture, precision, N, K + 1,
+ * floor(log2(tiles))) - tiles being the 64-ADO blocks of all of the call's
+ * instances with that N and K + 1 - times each distinct shape on its own
+ * launch (repeated first RK4 stages, which leave the run unchanged), then
+ * uses and remembers the fastest; later calls with that key reuse it.  If the
+ * environment variable HEOM_AUTOTUNE_CACHE names a file, entries are read
+ * from it on first use and new ones are appended (one JSON object per line).
+ *
+ * heom_tile_shape_count: number of shape slots (shapes are 0 .. count-1).
+ * heom_tile_shape_info: for N sites and K + 1 modes per site, the threads per
+ *   workgroup, target elements per wave and load chunk of `shape`; any output
+ *   may be NULL.  HEOM_E_UNSUPPORTED if the shape is not built for this N.
+ * heom_autotune_lookup: the tuned shape for that key on the current device,
+ *   or -1 if not tuned yet; us_per_shape [count] (or NULL) receives the
+ *   measured microseconds per first-stage launch of each shape, -1 where a
+ *   shape was not timed.
+ * heom_autotune_clear: forgets every tuned entry of the process (entries in
+ *   the cache file are read again on next use). */
+int heom_tile_shape_count(void);
+int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision, int32_t shape,
+                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk);
+int heom_autotune_lookup(int32_t n_sites, int32_t modes_per_site, int precision, int64_t n_tiles,
+                         int32_t *shape, double *us_per_shape);
+void heom_autotune_clear(void);
 
 /* Releases a handle and its device tables.  NULL is accepted. */
 void heom_destroy(heom_hierarchy *h);

@@ -24,20 +24,27 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
-SOURCES = ["params.cpp", "hierarchy.cpp", "runtime.cpp", "kernels_dispatch.hip",
-           "kernels_lane.hip", "kernels_tile_small.hip", "kernels_tile_7.hip",
-           "kernels_tile_8.hip", "kernels_tile_9_10.hip", "kernels_tile_11.hip",
-           "kernels_tile_12.hip"]
+# (source, tile launch shape it is compiled for, or None).  The tile units of
+# N <= 8 are compiled once per shape (the autotuner's candidates); N = 9..12
+# in the default shape only.
+_SHAPES = 3
+SOURCES = ([("params.cpp", None), ("hierarchy.cpp", None), ("runtime.cpp", None),
+            ("autotune.cpp", None), ("kernels_dispatch.hip", None), ("kernels_lane.hip", None)] +
+           [(f"kernels_tile_{u}.hip", s) for u in ("small", "7", "8") for s in range(_SHAPES)] +
+           [(f"kernels_tile_{u}.hip", 0) for u in ("9_10", "11", "12")])
 # The largest translation units first, so the parallel build ends sooner.
-_ORDER = ["kernels_tile_12.hip", "kernels_tile_11.hip", "kernels_tile_9_10.hip",
-          "kernels_tile_8.hip", "kernels_tile_7.hip"]
+_FIRST = ["kernels_tile_12.hip", "kernels_tile_11.hip", "kernels_tile_9_10.hip",
+          "kernels_tile_8.hip", "kernels_tile_small.hip", "kernels_tile_7.hip"]
 
 
-def _compile(src: str, defines=(), build_dir: str = BUILD_DIR) -> str:
-    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+def _compile(unit, defines=(), build_dir: str = BUILD_DIR) -> str:
+    src, shape = unit
+    stem = os.path.basename(src) + ("" if shape is None else f".s{shape}")
+    obj = os.path.join(build_dir, stem + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *COMMON, *[f"-D{d}" for d in defines], *lang, "-c", os.path.join(CSRC, src),
-           "-o", obj]
+    extra = [] if shape is None else [f"-DHEOM_SHAPE={shape}"]
+    cmd = [HIPCC, *COMMON, *[f"-D{d}" for d in defines], *extra, *lang, "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -50,7 +57,7 @@ def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BU
     `defines` are extra preprocessor definitions (tuning knobs of the kernels).
     """
     os.makedirs(build_dir, exist_ok=True)
-    order = _ORDER + [s for s in SOURCES if s not in _ORDER]
+    order = sorted(SOURCES, key=lambda u: _FIRST.index(u[0]) if u[0] in _FIRST else len(_FIRST))
     workers = max(1, min(len(order), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(lambda src: _compile(src, defines, build_dir), order))

@@ -1,0 +1,183 @@
+// autotune.cpp -- launch-shape autotuner of the tile stage kernel.
+//
+// The tile kernel is compiled in several launch shapes (waves per workgroup,
+// packed elements per wave, elements whose gathers are in flight together;
+// tile_shape in stage_kernels.h).  Which one is fastest depends on the size of
+// the launch: a launch of a few hundred tiles is latency-bound and prefers
+// long load batches, a launch of thousands of tiles is bandwidth-bound and
+// prefers shapes that keep more workgroups resident.  The tuner keys its
+// choice on (GPU architecture, precision, N, K+1, floor(log2(tiles))), times
+// every candidate once per key on the caller's own launch (see run_impl), and
+// remembers the fastest for the life of the process.  If HEOM_AUTOTUNE_CACHE
+// names a file, its entries are read on first use and new entries are
+// appended to it, one JSON object per line.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "heom_internal.h"
+
+namespace heom {
+
+namespace {
+
+struct Entry {
+  int shape = -1;
+  double us[kMaxTileShapes];
+};
+
+// (arch, mixed, N, K+1, floor(log2(tiles)))
+typedef std::tuple<std::string, int, int, int, int> Key;
+
+std::mutex g_mu;
+std::map<Key, Entry> g_cache;
+bool g_file_read = false;
+
+const char *cache_path() {
+  const char *p = std::getenv("HEOM_AUTOTUNE_CACHE");
+  return (p && p[0]) ? p : nullptr;
+}
+
+int log2_floor(int64_t x) {
+  int r = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+std::string arch_of(int device) {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = names.find(device);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop;
+  std::string name = "unknown";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    name = prop.gcnArchName;
+    const size_t colon = name.find(':');  // drop target features
+    if (colon != std::string::npos) name.resize(colon);
+  }
+  names[device] = name;
+  return name;
+}
+
+// One line of the cache file:
+// {"arch": "gfx950", "precision": 0, "N": 7, "KP": 1, "tiles_log2": 8, "shape": 1,
+//  "us": [10.6, 9.8, 12.0]}
+void read_file_locked() {
+  if (g_file_read) return;
+  g_file_read = true;
+  const char *path = cache_path();
+  if (!path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char arch[64] = {0};
+    int prec, N, KP, tl, shape;
+    double us[kMaxTileShapes];
+    for (double &u : us) u = -1.0;
+    const int got = std::sscanf(line,
+                                " {\"arch\": \"%63[^\"]\", \"precision\": %d, \"N\": %d, \"KP\": %d, "
+                                "\"tiles_log2\": %d, \"shape\": %d, \"us\": [%lf, %lf, %lf]",
+                                arch, &prec, &N, &KP, &tl, &shape, &us[0], &us[1], &us[2]);
+    if (got < 6 || shape < 0 || shape >= kMaxTileShapes) continue;  // not an entry
+    Entry e;
+    e.shape = shape;
+    for (int s = 0; s < kMaxTileShapes; ++s) e.us[s] = us[s];
+    g_cache[Key(arch, prec, N, KP, tl)] = e;
+  }
+  std::fclose(f);
+}
+
+void append_file_locked(const Key &k, const Entry &e) {
+  const char *path = cache_path();
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;  // the in-memory entry still holds
+  std::fprintf(f,
+               "{\"arch\": \"%s\", \"precision\": %d, \"N\": %d, \"KP\": %d, \"tiles_log2\": %d, "
+               "\"shape\": %d, \"us\": [%.3f, %.3f, %.3f]}\n",
+               std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+               std::get<4>(k), e.shape, e.us[0], e.us[1], e.us[2]);
+  std::fclose(f);
+}
+
+}  // namespace
+
+static_assert(kMaxTileShapes == 3, "the cache line format holds three timings");
+
+int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
+                    const std::function<int(int, double *)> &time_shape, int *shape_out) {
+  const Key key(arch_of(device), mixed ? 1 : 0, N, KP, log2_floor(n_tiles));
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    read_file_locked();
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      *shape_out = it->second.shape;
+      return HEOM_OK;
+    }
+  }
+  // Time the distinct candidates (shapes with the same launch configuration
+  // as an earlier one are the same kernel in effect and are skipped).
+  Entry e;
+  for (double &u : e.us) u = -1.0;
+  int seen_threads[kMaxTileShapes], seen_chunk[kMaxTileShapes], n_seen = 0;
+  double best = 0.0;
+  for (int s = 0; s < kMaxTileShapes; ++s) {
+    int threads = 0, epw = 0, chunk = 0;
+    if (!tile_shape_info(N, KP, mixed, s, &threads, &epw, &chunk)) continue;
+    bool dup = false;
+    for (int q = 0; q < n_seen; ++q)
+      dup = dup || (seen_threads[q] == threads && seen_chunk[q] == chunk);
+    if (dup) continue;
+    seen_threads[n_seen] = threads;
+    seen_chunk[n_seen] = chunk;
+    ++n_seen;
+    double us = 0.0;
+    int rc = time_shape(s, &us);
+    if (rc) return rc;
+    e.us[s] = us;
+    if (e.shape < 0 || us < best) {
+      e.shape = s;
+      best = us;
+    }
+  }
+  if (e.shape < 0) return fail(HEOM_E_UNSUPPORTED, "no tile launch shape for this hierarchy");
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto ins = g_cache.emplace(key, e);
+  if (ins.second) append_file_locked(key, e);
+  *shape_out = ins.first->second.shape;
+  return HEOM_OK;
+}
+
+int autotune_lookup(int device, bool mixed, int N, int KP, int64_t n_tiles, int *shape,
+                    double *us) {
+  const Key key(arch_of(device), mixed ? 1 : 0, N, KP, log2_floor(n_tiles));
+  std::lock_guard<std::mutex> lock(g_mu);
+  read_file_locked();
+  auto it = g_cache.find(key);
+  *shape = it == g_cache.end() ? -1 : it->second.shape;
+  if (us)
+    for (int s = 0; s < kMaxTileShapes; ++s) us[s] = it == g_cache.end() ? -1.0 : it->second.us[s];
+  return HEOM_OK;
+}
+
+void autotune_clear() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_cache.clear();
+  g_file_read = false;
+}
+
+}  // namespace heom

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -88,6 +89,9 @@ struct InstDesc {
 //  kGeneric: any N, complex H; one lane per ADO, reads from the planes
 enum class KernelKind { kTile, kLane, kGeneric };
 
+// Launch shapes of the tile kernel (the autotuner's candidates).
+constexpr int kMaxTileShapes = 3;
+
 // A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
 struct WorkItem {
   int32_t inst;
@@ -132,5 +136,17 @@ int fail(int status, const std::string &msg);
 int build_params(const heom_system *sys, heom_hierarchy *h);
 // hierarchy.cpp
 int build_tables(heom_hierarchy *h);
+// kernels_dispatch.hip: whether the tile kernel exists for (N, K+1, storage)
+// in launch shape `shape`, and that shape's parameters.
+bool tile_shape_info(int N, int KP, bool mixed, int shape, int *threads, int *elems_per_wave,
+                     int *chunk);
+// autotune.cpp: the launch shape of a tile group of n_tiles tiles, from the
+// cache or, for a new key, by timing each candidate with time_shape(shape,
+// &microseconds_per_launch).
+int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
+                    const std::function<int(int, double *)> &time_shape, int *shape_out);
+int autotune_lookup(int device, bool mixed, int N, int KP, int64_t n_tiles, int *shape,
+                    double *us);
+void autotune_clear();
 
 }  // namespace heom

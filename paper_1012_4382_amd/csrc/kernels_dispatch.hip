@@ -5,42 +5,66 @@
 
 namespace heom {
 
-StageKernel tile_kernel_part_small(int N, int KP, bool mixed);
-StageKernel tile_kernel_part_7(int N, int KP, bool mixed);
-StageKernel tile_kernel_part_8(int N, int KP, bool mixed);
-StageKernel tile_kernel_part_9_10(int N, int KP, bool mixed);
-StageKernel tile_kernel_part_11(int N, int KP, bool mixed);
-StageKernel tile_kernel_part_12(int N, int KP, bool mixed);
+typedef StageKernel (*TilePart)(int N, int KP, bool mixed);
+// Tile instances by shape: N <= 8 in every shape, N = 9..12 in shape 0 only.
+StageKernel tile_kernel_part_small_s0(int, int, bool);
+StageKernel tile_kernel_part_small_s1(int, int, bool);
+StageKernel tile_kernel_part_small_s2(int, int, bool);
+StageKernel tile_kernel_part_7_s0(int, int, bool);
+StageKernel tile_kernel_part_7_s1(int, int, bool);
+StageKernel tile_kernel_part_7_s2(int, int, bool);
+StageKernel tile_kernel_part_8_s0(int, int, bool);
+StageKernel tile_kernel_part_8_s1(int, int, bool);
+StageKernel tile_kernel_part_8_s2(int, int, bool);
+StageKernel tile_kernel_part_9_10_s0(int, int, bool);
+StageKernel tile_kernel_part_11_s0(int, int, bool);
+StageKernel tile_kernel_part_12_s0(int, int, bool);
 StageKernel lane_kernel_ptr(int N, int KP, bool mixed);
 
 namespace {
 
-StageKernel tile_kernel(int N, int KP, bool mixed) {
-  StageKernel k = nullptr;
-  if (!k) k = tile_kernel_part_small(N, KP, mixed);
-  if (!k) k = tile_kernel_part_7(N, KP, mixed);
-  if (!k) k = tile_kernel_part_8(N, KP, mixed);
-  if (!k) k = tile_kernel_part_9_10(N, KP, mixed);
-  if (!k) k = tile_kernel_part_11(N, KP, mixed);
-  if (!k) k = tile_kernel_part_12(N, KP, mixed);
-  return k;
+static_assert(kTileShapes == 3, "one row of tile parts per shape");
+constexpr TilePart kTileParts[kTileShapes][6] = {
+    {&tile_kernel_part_small_s0, &tile_kernel_part_7_s0, &tile_kernel_part_8_s0,
+     &tile_kernel_part_9_10_s0, &tile_kernel_part_11_s0, &tile_kernel_part_12_s0},
+    {&tile_kernel_part_small_s1, &tile_kernel_part_7_s1, &tile_kernel_part_8_s1, nullptr, nullptr,
+     nullptr},
+    {&tile_kernel_part_small_s2, &tile_kernel_part_7_s2, &tile_kernel_part_8_s2, nullptr, nullptr,
+     nullptr},
+};
+
+StageKernel tile_kernel(int N, int KP, bool mixed, int shape) {
+  if (shape < 0 || shape >= kTileShapes) return nullptr;
+  for (TilePart part : kTileParts[shape]) {
+    StageKernel k = part ? part(N, KP, mixed) : nullptr;
+    if (k) return k;
+  }
+  return nullptr;
 }
 
 }  // namespace
 
 bool has_fixed_kernel(int N, int KP) { return lane_kernel_ptr(N, KP, false) != nullptr; }
 
-bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false) != nullptr; }
+bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false, 0) != nullptr; }
 
-int tile_threads(int N, bool mixed) { return 64 * tile_waves_for(N, !mixed); }
+bool tile_shape_info(int N, int KP, bool mixed, int shape, int *threads, int *elems_per_wave,
+                     int *chunk) {
+  if (!tile_kernel(N, KP, mixed, shape)) return false;
+  const TileShape sh = tile_shape(!mixed, shape);
+  if (threads) *threads = 64 * tile_waves(N, !mixed, shape);
+  if (elems_per_wave) *elems_per_wave = sh.elems_per_wave;
+  if (chunk) *chunk = sh.chunk;
+  return true;
+}
 
-hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
-                        const WorkItem *work, int n_items, int block, int stage, double coef,
-                        int hist_slot, hipStream_t stream) {
+hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
+                        const InstDesc *descs, const WorkItem *work, int n_items, int block,
+                        int stage, double coef, int hist_slot, hipStream_t stream) {
   StageKernel k = nullptr;
   switch (kind) {
     case KernelKind::kTile:
-      k = tile_kernel(N, KP, mixed);
+      k = tile_kernel(N, KP, mixed, shape);
       break;
     case KernelKind::kLane:
       k = lane_kernel_ptr(N, KP, mixed);

@@ -25,10 +25,9 @@ namespace heom {
 // stage_kernels.hip
 bool has_fixed_kernel(int N, int KP);
 bool has_tile_kernel(int N, int KP);
-int tile_threads(int N, bool mixed);
-hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, const InstDesc *descs,
-                        const WorkItem *work, int n_items, int block, int stage, double coef,
-                        int hist_slot, hipStream_t stream);
+hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
+                        const InstDesc *descs, const WorkItem *work, int n_items, int block,
+                        int stage, double coef, int hist_slot, hipStream_t stream);
 hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
                        int block, hipStream_t stream);
 hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
@@ -268,9 +267,19 @@ struct StepGraph {
 struct Group {
   KernelKind kind;
   int N, KP;
+  int shape;  // tile launch shape (kTile only)
   int ados_per_item, threads;
-  int64_t item_begin, n_items;
+  int64_t item_begin, n_items, n_tiles;  // n_tiles: items that are not padding
 };
+
+// First-stage launches timed per candidate shape by the autotuner (after one
+// untimed launch).
+constexpr int kTuneReps = 5;
+
+// Tile launch shape forced by the flags (HEOM_TILE_SHAPE(s)), or -1.
+int forced_shape(int flags) { return ((flags >> 8) & 0xf) - 1; }
+
+constexpr int kShapeFlagMask = 0xf00;
 
 // Where the device data of one call live: each instance's regions (offsets
 // relative to its own base), the headers that identify the runs held there,
@@ -298,6 +307,20 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
   if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
   if (n_steps < 0) return fail(HEOM_E_INVALID, "n_steps must be >= 0");
   if (record_every < 1) return fail(HEOM_E_INVALID, "record_every must be >= 1");
+  // A forced tile launch shape must exist for every instance the tile kernel
+  // will run.
+  const int forced = forced_shape(flags);
+  if (forced >= kMaxTileShapes) return fail(HEOM_E_INVALID, "tile launch shape out of range");
+  if (forced >= 0 && !(flags & (HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)))
+    for (int k = 0; k < n; ++k) {
+      const heom_hierarchy *h = hs[k];
+      const bool mixed = precision == HEOM_FP32_MIXED;
+      if (h->h_real && tile_shape_info(h->N, h->KP, mixed, 0, nullptr, nullptr, nullptr) &&
+          !tile_shape_info(h->N, h->KP, mixed, forced, nullptr, nullptr, nullptr))
+        return fail(HEOM_E_UNSUPPORTED, "tile launch shape " + std::to_string(forced) +
+                                            " is not built for N=" + std::to_string(h->N) +
+                                            ", K+1=" + std::to_string(h->KP));
+    }
   return HEOM_OK;
 }
 
@@ -384,9 +407,11 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     g.kind = static_cast<KernelKind>(std::get<0>(kv.first));
     g.N = std::get<1>(kv.first);
     g.KP = std::get<2>(kv.first);
+    g.shape = 0;
     if (g.kind == KernelKind::kTile) {
       g.ados_per_item = 64;
-      g.threads = tile_threads(g.N, mixed);
+      if (!tile_shape_info(g.N, g.KP, mixed, 0, &g.threads, nullptr, nullptr))
+        return fail(HEOM_E_UNSUPPORTED, "no tile kernel for this hierarchy");
     } else {
       g.ados_per_item = block_ados();
       g.threads = g.ados_per_item;
@@ -396,6 +421,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     for (int k : kv.second)
       for (int64_t first = 0; first < hs[k]->n_ados; first += g.ados_per_item)
         mine.push_back({k, static_cast<int32_t>(first)});
+    g.n_tiles = static_cast<int64_t>(mine.size());
     if (xcd_remap()) {
       // Workgroup b runs on XCD b % kXcds.  Give XCD x the x-th contiguous
       // eighth of the list (consecutive tiles of the same instance), so that
@@ -494,12 +520,51 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     ++slot;
   }
   const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
+  // Launch shape of each tile group: forced by the flags, the default, or
+  // the autotuner's.  The tuner times repeated first stages, which read the
+  // state and write only the first stage buffer, so the run is unchanged.
+  for (Group &g : groups) {
+    if (g.kind != KernelKind::kTile) continue;
+    int shape = forced_shape(flags);  // validated when the groups were formed
+    if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = 0;
+    if (shape < 0) {
+      auto time_shape = [&](int s, double *us) -> int {
+        int threads = 0;
+        tile_shape_info(g.N, g.KP, mixed, s, &threads, nullptr, nullptr);
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        int rc = HEOM_OK;
+        auto launch = [&]() {
+          return launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.item_begin,
+                              static_cast<int>(g.n_items), threads, 0, coef[0], -1, stream);
+        };
+        hipError_t e = hipEventCreate(&ev[0]);
+        if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+        for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) rc = dev_fail(e, "autotune timing");
+        for (hipEvent_t x : ev)
+          if (x) (void)hipEventDestroy(x);
+        *us = 1000.0 * static_cast<double>(ms) / kTuneReps;
+        return rc;
+      };
+      int rc = autotune_choose(device, mixed, g.N, g.KP, g.n_tiles, time_shape, &shape);
+      if (rc) return rc;
+    }
+    g.shape = shape;
+    tile_shape_info(g.N, g.KP, mixed, shape, &g.threads, nullptr, nullptr);
+  }
   // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.
   auto enqueue_step = [&](hipStream_t s) -> hipError_t {
     for (int st = 0; st < 4; ++st)
       for (const Group &g : groups) {
-        hipError_t e = launch_stage(g.kind, mixed, g.N, g.KP, d_descs, d_work + g.item_begin,
-                                    static_cast<int>(g.n_items), g.threads, st, coef[st], -1, s);
+        hipError_t e = launch_stage(g.kind, mixed, g.N, g.KP, g.shape, d_descs,
+                                    d_work + g.item_begin, static_cast<int>(g.n_items), g.threads,
+                                    st, coef[st], -1, s);
         if (e != hipSuccess) return e;
       }
     return hipSuccess;
@@ -563,7 +628,8 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
                    void *d_ws, size_t ws_bytes, void *hip_stream, double *const *rho_outs,
                    double *const *sinks_outs) {
   int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, record_every,
-                        HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH);
+                        HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
+                            HEOM_NO_AUTOTUNE | kShapeFlagMask);
   if (rc) return rc;
   const Layout L = make_layout(hs, n, precision);
   if (!d_ws) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
@@ -748,7 +814,8 @@ int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int 
                        double *const *rho_out, double *const *sinks_out) {
   try {
     int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, 1,
-                          HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH);
+                          HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
+                              HEOM_NO_AUTOTUNE | kShapeFlagMask);
     if (rc) return rc;
     if (!d_workspaces || !workspace_bytes || !start)
       return fail(HEOM_E_INVALID, "workspaces, sizes and start flags are required");
@@ -910,6 +977,40 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
   tail[2] = sc[2];
   return HEOM_OK;
 }
+
+int heom_tile_shape_count(void) { return kMaxTileShapes; }
+
+int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision, int32_t shape,
+                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk) {
+  if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
+    return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
+  if (shape < 0 || shape >= kMaxTileShapes) return fail(HEOM_E_INVALID, "shape out of range");
+  int t = 0, e = 0, c = 0;
+  if (!tile_shape_info(n_sites, modes_per_site, precision == HEOM_FP32_MIXED, shape, &t, &e, &c))
+    return fail(HEOM_E_UNSUPPORTED, "the tile kernel is not built for this N, K+1 and shape");
+  if (threads) *threads = t;
+  if (elems_per_wave) *elems_per_wave = e;
+  if (chunk) *chunk = c;
+  return HEOM_OK;
+}
+
+int heom_autotune_lookup(int32_t n_sites, int32_t modes_per_site, int precision, int64_t n_tiles,
+                         int32_t *shape, double *us_per_shape) {
+  if (!shape) return fail(HEOM_E_INVALID, "shape is NULL");
+  if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
+    return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
+  if (n_tiles < 1) return fail(HEOM_E_INVALID, "n_tiles must be >= 1");
+  int device = 0;
+  HEOM_HIP(hipGetDevice(&device), "hipGetDevice");
+  int s = -1;
+  int rc = autotune_lookup(device, precision == HEOM_FP32_MIXED, n_sites, modes_per_site, n_tiles,
+                           &s, us_per_shape);
+  if (rc) return rc;
+  *shape = s;
+  return HEOM_OK;
+}
+
+void heom_autotune_clear(void) { autotune_clear(); }
 
 void heom_destroy(heom_hierarchy *h) {
   if (!h) return;

@@ -133,24 +133,34 @@ __host__ __device__ constexpr int re_plane(int N, int a, int b) {
   return N + 2 * (a * N - a * (a + 1) / 2 + (b - a - 1));
 }
 
+// Fused multiply-add, a * b + c with one rounding.  The tile kernel writes
+// every multiply-add through this and turns off the compiler's own
+// contraction, so its rounding is fixed by the source and does not depend on
+// how a launch shape schedules the elements of a wave.
+__device__ __forceinline__ double fmad(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Sink flux of sigma_0 and the scalar part of one stage, then (last stage) the
 // history record.  `x0e(e)` returns packed element e of the stage input of
 // sigma_0, `newy(e)` the packed element e just written to the state.
 template <typename LoadX>
 __device__ __forceinline__ void scalar_update(const InstDesc &d, const StageBufs &b, int N,
                                               double coef, LoadX x0e) {
+#pragma clang fp contract(off)
   const ParamOffsets o = param_offsets(N, d.M);
   double ft = 0.0, fr = 0.0;
   for (int s = 0; s < N; ++s) {
     const double pop = x0e(s);
-    ft += d.params[o.trap + s] * pop;
-    fr += d.params[o.rec + s] * pop;
+    ft = fmad(d.params[o.trap + s], pop, ft);
+    fr = fmad(d.params[o.rec + s], pop, fr);
   }
   const double xq = b.xs[0];
   const double y_t = b.ys[0], y_r = b.ys[1], y_q = b.ys[2];
-  b.outs[0] = y_t + coef * ft;
-  b.outs[1] = y_r + coef * fr;
-  b.outs[2] = y_q + coef * xq;
+  b.outs[0] = fmad(coef, ft, y_t);
+  b.outs[1] = fmad(coef, fr, y_r);
+  b.outs[2] = fmad(coef, xq, y_q);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,42 +558,51 @@ __host__ __device__ constexpr int ent_im(int N, int r, int c) {
 }
 __host__ __device__ constexpr int ent_sg(int r, int c) { return r > c ? -1 : 1; }
 
-// Target packed elements per wave of the tile kernel, and how many of a
-// wave's elements have their global loads in flight together (one chunk), for
-// FP64 and FP32 storage.  Measured on the FMO-shaped 7-site workloads: FP64
-// does best with fewer, longer waves (so that all workgroups are resident at
-// its register use) and short load chunks; FP32 with more waves and longer
-// chunks.  Each can be overridden at build time.
-#ifndef HEOM_TILE_ELEMS_PER_WAVE_F64
-#define HEOM_TILE_ELEMS_PER_WAVE_F64 7
-#endif
-#ifndef HEOM_TILE_CHUNK_F64
-#define HEOM_TILE_CHUNK_F64 2
-#endif
-#ifndef HEOM_TILE_ELEMS_PER_WAVE_F32
-#define HEOM_TILE_ELEMS_PER_WAVE_F32 4
-#endif
-#ifndef HEOM_TILE_CHUNK_F32
-#define HEOM_TILE_CHUNK_F32 4
-#endif
+// Launch shapes of the tile kernel, the candidates of the autotuner: the
+// target number of packed elements per wave (which sets the waves per
+// workgroup, see tile_waves_for) and how many of a wave's elements have their
+// global loads in flight together (one chunk).  Shape 0 is the default:
+// measured on the FMO-shaped 7-site workloads, FP64 does best with fewer,
+// longer waves and short load chunks, FP32 with more waves and longer chunks.
+// Every shape computes each element with the same instructions in the same
+// order, so the results do not depend on the shape.
+struct TileShape {
+  int elems_per_wave, chunk;
+};
+constexpr int kTileShapes = kMaxTileShapes;
+__host__ __device__ constexpr TileShape tile_shape(bool fp64, int s) {
+  return fp64 ? (s == 0 ? TileShape{7, 2} : s == 1 ? TileShape{7, 7} : TileShape{2, 2})
+              : (s == 0 ? TileShape{4, 4} : s == 1 ? TileShape{4, 2} : TileShape{2, 2});
+}
 #ifndef HEOM_TILE_CHUNK_BARRIER
 #define HEOM_TILE_CHUNK_BARRIER 1
 #endif
 
 // Waves per tile workgroup: the divisor of the N(N+1)/2 packed elements
-// (at most 16) that gives closest to the target elements per wave.
-__host__ __device__ constexpr int tile_waves_for(int N, bool fp64) {
+// (at most 16) that gives closest to `target` elements per wave.
+__host__ __device__ constexpr int tile_waves_for(int N, int target) {
   const int P = N * (N + 1) / 2;
-  const int t = fp64 ? HEOM_TILE_ELEMS_PER_WAVE_F64 : HEOM_TILE_ELEMS_PER_WAVE_F32;
   int best = 1;
   for (int w = 1; w <= 16 && w <= P; ++w) {
     if (P % w) continue;
-    const int d_best = (t * best - P) < 0 ? P - t * best : t * best - P;
-    const int d_w = (t * w - P) < 0 ? P - t * w : t * w - P;
+    const int d_best = (target * best - P) < 0 ? P - target * best : target * best - P;
+    const int d_w = (target * w - P) < 0 ? P - target * w : target * w - P;
     if (d_w < d_best) best = w;
   }
   return best;
 }
+__host__ __device__ constexpr int tile_waves(int N, bool fp64, int s) {
+  return tile_waves_for(N, tile_shape(fp64, s).elems_per_wave);
+}
+
+// The tile units are compiled once per shape (HEOM_SHAPE); their instance
+// tables carry the shape in their names.
+#ifndef HEOM_SHAPE
+#define HEOM_SHAPE 0
+#endif
+#define HEOM_SHAPED_CAT(name, s) name##_s##s
+#define HEOM_SHAPED_EXPAND(name, s) HEOM_SHAPED_CAT(name, s)
+#define HEOM_SHAPED(name) HEOM_SHAPED_EXPAND(name, HEOM_SHAPE)
 
 template <typename T>
 struct TileCtx {
@@ -662,6 +681,7 @@ __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> 
 // values, RK4 stage update, store.  C is the arithmetic type.
 template <int N, int KP, int A, int B, typename C, typename T, bool X0SRC>
 __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads<C, KP> &L) {
+#pragma clang fp contract(off)
   constexpr int M = N * KP;
   constexpr int o_hg = 2 * N * N, o_dl = 2 * N * N + N, o_cr = 2 * N * N + 4 * N,
                 o_ci = 2 * N * N + 4 * N + M;
@@ -683,15 +703,15 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
     const C xkb_i = static_cast<C>(ent_sg(k, B)) * xe(ent_im(N, k, B));
     const C xak_r = xe(ent_re(N, A, k));
     const C xak_i = static_cast<C>(ent_sg(A, k)) * xe(ent_im(N, A, k));
-    sr += hak * xkb_r - xak_r * hkb;
-    si += hak * xkb_i - xak_i * hkb;
+    sr = fmad(-xak_r, hkb, fmad(hak, xkb_r, sr));
+    si = fmad(-xak_i, hkb, fmad(hak, xkb_i, si));
   }
   C ar = si, ai = -sr;
   const C xr = xe(E), xi = xe(ent_im(N, A, B));
   C dec = static_cast<C>(c.damp) + static_cast<C>(c.P[o_hg + A]) + static_cast<C>(c.P[o_hg + B]);
   if constexpr (A != B) dec += static_cast<C>(c.P[o_dl + A]) + static_cast<C>(c.P[o_dl + B]);
-  ar -= dec * xr;
-  ai -= dec * xi;
+  ar = fmad(-dec, xr, ar);
+  ai = fmad(-dec, xi, ai);
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int ma = A * KP + k;
@@ -701,8 +721,8 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
       // weighted by zero where the neighbour is missing.
       const C fa = c.sup[ma * kTile + lane] >= 0 ? C(1) : C(0);
       const C fb = c.sup[mb * kTile + lane] >= 0 ? C(1) : C(0);
-      ar += fb * L.ybi[k] - fa * L.yai[k];
-      ai += fa * L.yar[k] - fb * L.ybr[k];
+      ar = fmad(-fa, L.yai[k], fmad(fb, L.ybi[k], ar));
+      ai = fmad(-fb, L.ybr[k], fmad(fa, L.yar[k], ai));
     }
     // Shallower neighbours: + i n c Z (site A) - i n conj(c) Z (site B).
     const C na = static_cast<C>(c.socc[ma * kTile + lane]);
@@ -712,17 +732,17 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
     const C zai = (A == B) ? C(0) : L.zai[k];
     const C zbi = (A == B) ? C(0) : L.zbi[k];
     // i (car + i cai) z_a = -(cai zar + car zai) + i (car zar - cai zai)
-    ar -= cai * L.zar[k] + car * zai;
-    ai += car * L.zar[k] - cai * zai;
+    ar = fmad(-car, zai, fmad(-cai, L.zar[k], ar));
+    ai = fmad(-cai, zai, fmad(car, L.zar[k], ai));
     // -i (cbr - i cbi) z_b = (cbr zbi - cbi zbr) - i (cbr zbr + cbi zbi)
-    ar += cbr * zbi - cbi * L.zbr[k];
-    ai -= cbr * L.zbr[k] + cbi * zbi;
+    ar = fmad(-cbi, L.zbr[k], fmad(cbr, zbi, ar));
+    ai = fmad(-cbi, zbi, fmad(-cbr, L.zbr[k], ai));
   }
   // RK4 stage: out = y + coef * rhs (at stage 0 the state planes are the
   // stage input, so the loaded state equals the tile).
   const C coef = static_cast<C>(c.coef);
-  const C nr = L.str + coef * ar;
-  const C ni = ((A == B) ? C(0) : L.sti) + coef * ai;
+  const C nr = fmad(coef, ar, L.str);
+  const C ni = fmad(coef, ai, (A == B) ? C(0) : L.sti);
   if constexpr (X0SRC) {
     c.out0[E] = nr;
     if constexpr (A != B) c.out0[E + 1] = ni;
@@ -745,13 +765,12 @@ __device__ __forceinline__ void tile_chunk(const TileCtx<T> &c, std::integer_seq
    ...);
 }
 
-template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool X0SRC>
+template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T, bool X0SRC>
 __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int P = N * (N + 1) / 2;
   constexpr int count = (P - G + W - 1) / W;
   // An element gathers 4 neighbours per mode of its sites: with more modes
   // per site, fewer elements per chunk keep the loaded values in registers.
-  constexpr int CH0 = sizeof(T) == 8 ? HEOM_TILE_CHUNK_F64 : HEOM_TILE_CHUNK_F32;
   constexpr int CH = CH0 / KP > 0 ? CH0 / KP : 1;
   if constexpr (OFF < count) {
     constexpr int len = (count - OFF < CH) ? count - OFF : CH;
@@ -762,29 +781,30 @@ __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
 #if HEOM_TILE_CHUNK_BARRIER
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    tile_chunks<N, KP, G, W, OFF + CH, C, T, X0SRC>(c);
+    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T, X0SRC>(c);
   }
 }
 
 // Elements G, G + W, ... of every ADO of the tile (wave G of W).
-template <int N, int KP, int W, typename C, typename T, bool X0SRC, int G = 0>
+template <int N, int KP, int W, int CH0, typename C, typename T, bool X0SRC, int G = 0>
 __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
   if constexpr (G < W) {
     if (wave == G)
-      tile_chunks<N, KP, G, W, 0, C, T, X0SRC>(c);
+      tile_chunks<N, KP, G, W, CH0, 0, C, T, X0SRC>(c);
     else
-      tile_dispatch<N, KP, W, C, T, X0SRC, G + 1>(wave, c);
+      tile_dispatch<N, KP, W, CH0, C, T, X0SRC, G + 1>(wave, c);
   }
 }
 
-template <int N, int KP, typename T>
-__global__ void __launch_bounds__(64 * tile_waves_for(N, sizeof(T) == 8),
+template <int N, int KP, typename T, int SHAPE>
+__global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                                   HEOM_TILE_MIN_WAVES_PER_SIMD)
     stage_tile(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
                double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
   constexpr int N2 = N * N;
   constexpr int M = N * KP;
-  constexpr int W = tile_waves_for(N, sizeof(T) == 8);
+  constexpr int W = tile_waves(N, sizeof(T) == 8, SHAPE);
+  constexpr int CH0 = tile_shape(sizeof(T) == 8, SHAPE).chunk;
   constexpr bool MIXED = sizeof(T) == 4;
   __shared__ T sx[(N2 + 1) * kTile];
   __shared__ int32_t sup[M * kTile];
@@ -845,7 +865,7 @@ __global__ void __launch_bounds__(64 * tile_waves_for(N, sizeof(T) == 8),
   double damp = 0.0;
 #pragma unroll
   for (int m = 0; m < M; ++m)
-    damp += static_cast<double>(socc[m * kTile + lane]) * P[2 * N * N + 4 * N + 2 * M + m];
+    damp = fmad(static_cast<double>(socc[m * kTile + lane]), P[2 * N * N + 4 * N + 2 * M + m], damp);
   TileCtx<T> ctx{P,
                  sx,
                  sup,
@@ -862,12 +882,12 @@ __global__ void __launch_bounds__(64 * tile_waves_for(N, sizeof(T) == 8),
                  lane,
                  damp,
                  coef};
-  tile_dispatch<N, KP, W, T, T, false>(wave, ctx);
+  tile_dispatch<N, KP, W, CH0, T, T, false>(wave, ctx);
   const bool is0 = (i == 0);
   if constexpr (MIXED) {
     // sigma_0 again, in FP64 from its FP64 copy; these writes follow the FP32
     // ones above in program order, so they are the ones that remain.
-    if (is0) tile_dispatch<N, KP, W, double, T, true>(wave, ctx);
+    if (is0) tile_dispatch<N, KP, W, CH0, double, T, true>(wave, ctx);
   }
   if (is0 && wave == 0) {
     scalar_update(d, bufs, N, coef, [&](int s) {

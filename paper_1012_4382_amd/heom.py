@@ -30,7 +30,22 @@ HEOM_RESUME = 1
 HEOM_GENERIC_KERNEL = 2
 HEOM_LANE_KERNEL = 4
 HEOM_NO_GRAPH = 8
+HEOM_NO_AUTOTUNE = 16
 KERNELS = {"auto": 0, "generic": HEOM_GENERIC_KERNEL, "lane": HEOM_LANE_KERNEL}
+
+
+def tile_shape_flag(shape: int) -> int:
+    """HEOM_TILE_SHAPE(shape): forces tile launch shape `shape`."""
+    return ((int(shape) + 1) & 0xF) << 8
+
+
+def _flags(resume: bool, kernel: str, graphs: bool, tile_shape, autotune: bool) -> int:
+    f = (HEOM_RESUME if resume else 0) | KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
+    if tile_shape is not None:
+        f |= tile_shape_flag(tile_shape)
+    elif not autotune:
+        f |= HEOM_NO_AUTOTUNE
+    return f
 
 PRECISIONS = {"fp64": HEOM_FP64, "fp32": HEOM_FP32_MIXED, HEOM_FP64: HEOM_FP64,
               HEOM_FP32_MIXED: HEOM_FP32_MIXED}
@@ -87,6 +102,11 @@ _SIGNATURES = [
     ("heom_advance_slots", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, ctypes.c_int, _P(_vp),
                                           _P(_sz), _P(_i32), _P(_P(_d)), _d, _i64, _vp, _sz, _vp,
                                           _P(_P(_d)), _P(_P(_d))]),
+    ("heom_tile_shape_count", ctypes.c_int, []),
+    ("heom_tile_shape_info", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i32, _P(_i32), _P(_i32),
+                                            _P(_i32)]),
+    ("heom_autotune_lookup", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i64, _P(_i32), _P(_d)]),
+    ("heom_autotune_clear", None, []),
     ("heom_destroy", None, [_vp]),
     ("heom_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("heom_last_error", ctypes.c_char_p, []),
@@ -221,13 +241,16 @@ def _ws_args(ws):
 
 def propagate(h: Hierarchy, rho0, dt_fs: float, n_steps: int, record_every: int = 1,
               precision="fp64", workspace=None, stream=None, resume: bool = False,
-              kernel: str = "auto", want_rho: bool = True, graphs: bool = True):
-    """Runs heom_propagate (kernel: "auto", or the diagnostic "lane" / "generic").  Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
+              kernel: str = "auto", want_rho: bool = True, graphs: bool = True,
+              tile_shape=None, autotune: bool = True):
+    """Runs heom_propagate (kernel: "auto", or the diagnostic "lane" / "generic";
+    tile_shape forces a tile launch shape, autotune=False uses shape 0).
+    Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(h.workspace_bytes[prec])
     ptr, nbytes = _ws_args(workspace)
-    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
+    flags = _flags(resume, kernel, graphs, tile_shape, autotune)
     r0 = None
     if rho0 is not None:
         r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
@@ -251,14 +274,15 @@ def batch_workspace_bytes(hs, precision="fp64") -> int:
 
 def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1,
                     precision="fp64", workspace=None, stream=None, resume: bool = False,
-                    kernel: str = "auto", want_rho: bool = True, graphs: bool = True):
+                    kernel: str = "auto", want_rho: bool = True, graphs: bool = True,
+                    tile_shape=None, autotune: bool = True):
     """Runs heom_propagate_batch.  Returns (list of rho | None, sinks [n, 3], workspace)."""
     n = len(hs)
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(batch_workspace_bytes(hs, precision))
     ptr, nbytes = _ws_args(workspace)
-    flags = (HEOM_RESUME if resume else 0) | KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
+    flags = _flags(resume, kernel, graphs, tile_shape, autotune)
     DP = ctypes.POINTER(ctypes.c_double)
     keep = []
     r0 = (DP * n)()
@@ -317,7 +341,7 @@ def slots_scratch_bytes(hs) -> int:
 
 def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scratch,
                   precision="fp64", stream=None, kernel: str = "auto", graphs: bool = True,
-                  want_rho: bool = True):
+                  want_rho: bool = True, tile_shape=None, autotune: bool = True):
     """Runs heom_advance_slots.  Returns (list of final rho [N, N] | None, sinks [n, 3])."""
     n = len(hs)
     DP = ctypes.POINTER(ctypes.c_double)
@@ -340,8 +364,40 @@ def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scra
         so[k] = sinks[k].ctypes.data_as(DP)
     arr = (ctypes.c_void_p * n)(*[h.handle.value for h in hs])
     sptr, sbytes = _ws_args(scratch)
-    flags = KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
+    flags = _flags(False, kernel, graphs, tile_shape, autotune)
     _check(library().heom_advance_slots(arr, n, PRECISIONS[precision], flags, wsp, wsb, st, r0,
                                         float(dt_fs), int(n_steps), sptr, sbytes,
                                         _stream_handle(stream), ro, so), "heom_advance_slots")
     return rhos, sinks
+
+
+def tile_shape_count() -> int:
+    return int(library().heom_tile_shape_count())
+
+
+def tile_shape_info(n_sites: int, modes_per_site: int, precision="fp64", shape: int = 0):
+    """(threads per workgroup, target elements per wave, load chunk) of a tile
+    launch shape, or None if that shape is not built for n_sites."""
+    t, e, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    st = library().heom_tile_shape_info(int(n_sites), int(modes_per_site), PRECISIONS[precision],
+                                        int(shape), ctypes.byref(t), ctypes.byref(e),
+                                        ctypes.byref(c))
+    if st == HEOM_E_UNSUPPORTED:
+        return None
+    _check(st, "heom_tile_shape_info")
+    return t.value, e.value, c.value
+
+
+def autotune_lookup(n_sites: int, modes_per_site: int, n_tiles: int, precision="fp64"):
+    """(tuned shape or -1, microseconds per first-stage launch of each shape,
+    -1 where not timed) for the current device."""
+    shape = ctypes.c_int32()
+    us = np.full(tile_shape_count(), -1.0)
+    _check(library().heom_autotune_lookup(int(n_sites), int(modes_per_site),
+                                          PRECISIONS[precision], int(n_tiles),
+                                          ctypes.byref(shape), _dp(us)), "heom_autotune_lookup")
+    return shape.value, us
+
+
+def autotune_clear():
+    library().heom_autotune_clear()

@@ -1,0 +1,145 @@
+"""GPU: launch shapes of the tile stage kernel and their autotuner.
+
+Every shape computes each packed element with the same instructions, so the
+results must be bitwise identical across shapes; the autotuner times repeated
+first RK4 stages on the caller's own launch, which must leave the run
+unchanged.  Parity of the default path with the FP64 oracle is covered by
+test_gpu_parity.py; one case here also checks a forced shape against it.
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1012_4382_amd import heom, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU (run with -m 'not gpu' on CPU)")
+    heom.library()
+    yield
+    heom.autotune_clear()
+
+
+def _chain8(seed):
+    rng = np.random.default_rng(seed)
+    eps = rng.normal(12400.0, 100.0, 8)
+    J = rng.normal(-80.0, 20.0, 7)
+    H = np.diag(eps) + np.diag(J, 1) + np.diag(J, -1)
+    trap, rec = workloads.fmo_sinks(8, trap_site=8)
+    return workloads.system(H, trap=trap, rec=rec)
+
+
+def _cases():
+    fmo = workloads.fmo_like(seed=2, site=1, depth=4)
+    sweep = workloads.sweep_instance(3)  # N = 7, one Matsubara term per bath
+    return {
+        "fmo7_d4": (fmo["system"], 4, fmo["rho0"]),
+        "sweep7_k1_d3": (sweep["system"], 3, sweep["rho0"]),
+        "chain8_d3": (_chain8(5), 3, workloads.site_state(8, 1)),
+        "three_site_d5": (workloads.system(fmo["system"]["H"][:3, :3]), 5,
+                          workloads.site_state(3, 1)),
+    }
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["fmo7_d4", "sweep7_k1_d3", "chain8_d3", "three_site_d5"])
+def test_shapes_are_bitwise_identical(case, precision):
+    sys_, depth, rho0 = _cases()[case]
+    h = heom.Hierarchy(sys_, depth)
+    N, KP = h.N, h.n_modes // h.N
+    shapes = [s for s in range(heom.tile_shape_count())
+              if heom.tile_shape_info(N, KP, precision, s) is not None]
+    assert len(shapes) == heom.tile_shape_count()
+    ref = None
+    for s in shapes:
+        _say(f"case: {case} N={N} K+1={KP} depth={depth} {precision} shape={s} "
+             f"{heom.tile_shape_info(N, KP, precision, s)}")
+        rho, sinks, ws = heom.propagate(h, rho0, 1.0, 200, record_every=5, precision=precision,
+                                        tile_shape=s)
+        state, sc = heom.read_state(h, ws, precision)
+        if ref is None:
+            ref = (rho, sinks, state)
+            continue
+        assert np.array_equal(rho, ref[0]), s
+        assert np.array_equal(sinks, ref[1]), s
+        assert np.array_equal(state, ref[2]), s
+
+
+def test_forced_shape_matches_oracle():
+    w = workloads.fmo_like(seed=0, site=6, depth=3, steps=300)
+    h = heom.Hierarchy(w["system"], w["depth"])
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], 1.0, 300, record_every=10)
+    for s in range(heom.tile_shape_count()):
+        _say(f"case: fmo_like seed0 site6 depth3 300 steps shape={s}")
+        rho, sinks, _ = heom.propagate(h, w["rho0"], 1.0, 300, record_every=10, tile_shape=s)
+        assert float(np.max(np.abs(rho - ref["rho"])) / np.max(np.abs(ref["rho"]))) <= 1e-10
+        assert np.max(np.abs(sinks - ref["scalars"])) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuner_choice_is_cached_and_leaves_the_run_unchanged(precision):
+    ws_ = workloads.fmo_like_batch(seeds=(0, 1), sites=(1, 6), depth=5, steps=100)
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in ws_]
+    r0 = [w["rho0"] for w in ws_]
+    n_tiles = sum((h.n_ados + 63) // 64 for h in hs)
+    heom.autotune_clear()
+    assert heom.autotune_lookup(7, 1, n_tiles, precision)[0] == -1
+    _say(f"case: autotune fmo_like batch of 4, depth 5, {precision}")
+    tuned, s_tuned, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5,
+                                             precision=precision)
+    shape, us = heom.autotune_lookup(7, 1, n_tiles, precision)
+    assert 0 <= shape < heom.tile_shape_count()
+    timed = us[us >= 0]
+    assert len(timed) >= 2 and np.all(timed > 0) and us[shape] == np.min(timed)
+    _say(f"  tuned shape {shape}, us per first stage {us.tolist()}")
+    plain, s_plain, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5,
+                                             precision=precision, autotune=False)
+    for a, b in zip(tuned, plain):
+        assert np.array_equal(a, b)
+    assert np.array_equal(s_tuned, s_plain)
+    again, _, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5, precision=precision)
+    shape2, us2 = heom.autotune_lookup(7, 1, n_tiles, precision)
+    assert shape2 == shape and np.array_equal(us2, us)  # not re-timed
+    for a, b in zip(again, plain):
+        assert np.array_equal(a, b)
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("HEOM_AUTOTUNE_CACHE", str(path))
+    try:
+        heom.autotune_clear()
+        w = workloads.fmo_like(seed=1, site=1, depth=3, steps=64)  # 120 ADOs: 2 tiles
+        h = heom.Hierarchy(w["system"], w["depth"])
+        _say("case: autotune cache file, fmo_like depth 3")
+        rho, _, _ = heom.propagate(h, w["rho0"], 1.0, 64, record_every=8)
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1
+        entry = json.loads(lines[0])
+        assert (entry["N"], entry["KP"], entry["precision"], entry["tiles_log2"]) == (7, 1, 0, 1)
+        assert entry["shape"] == heom.autotune_lookup(7, 1, 2)[0]
+        # An entry in the file is used as it stands (here: shape 2) and not re-timed.
+        entry["shape"] = 2
+        path.write_text(json.dumps(entry) + "\n")
+        heom.autotune_clear()
+        assert heom.autotune_lookup(7, 1, 2)[0] == 2
+        rho2, _, _ = heom.propagate(h, w["rho0"], 1.0, 64, record_every=8)
+        assert len(path.read_text().splitlines()) == 1
+        assert np.array_equal(rho, rho2)
+    finally:
+        monkeypatch.delenv("HEOM_AUTOTUNE_CACHE")
+        heom.autotune_clear()

@@ -170,3 +170,41 @@ def test_product_path_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "heom_oracle" not in text, f
+
+
+def test_tile_shapes_and_forced_shape_validation():
+    """Launch shapes of the tile kernel: every N <= 12 has shape 0, N <= 8 all
+    shapes; a workgroup's waves divide the N(N+1)/2 packed elements; a forced
+    shape that is out of range or not built is rejected before device work."""
+    lib = heom.library()
+    count = heom.tile_shape_count()
+    assert count == 3
+    for N in range(1, 13):
+        P = N * (N + 1) // 2
+        for prec in ("fp64", "fp32"):
+            for s in range(count):
+                info = heom.tile_shape_info(N, 1, prec, s)
+                if s == 0 or N <= 8:
+                    assert info is not None, (N, prec, s)
+                if info is not None:
+                    threads, epw, chunk = info
+                    assert threads % 64 == 0 and 64 <= threads <= 1024
+                    assert P % (threads // 64) == 0 and epw >= 1 and chunk >= 1
+    assert heom.tile_shape_info(13, 1, "fp64", 0) is None
+    assert lib.heom_tile_shape_info(7, 1, 0, count, None, None, None) == heom.HEOM_E_INVALID
+    assert lib.heom_tile_shape_info(7, 1, 5, 0, None, None, None) == heom.HEOM_E_UNSUPPORTED
+
+    H = np.diag(np.linspace(12300.0, 12500.0, 12)) + np.diag(np.full(11, -80.0), 1) \
+        + np.diag(np.full(11, -80.0), -1)
+    h = heom.Hierarchy(workloads.system(H), 1)
+    r0 = np.ascontiguousarray(workloads.site_state(12, 1)).view(np.float64)
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: validation fails first
+
+    def call(flags):
+        return lib.heom_propagate(h.handle, 0, flags, heom._dp(r0), 1.0, 10, 1, fake, 1 << 30,
+                                  None, None, None)
+
+    assert call(heom.tile_shape_flag(1)) == heom.HEOM_E_UNSUPPORTED
+    assert "not built" in lib.heom_last_error().decode()
+    assert call(heom.tile_shape_flag(count)) == heom.HEOM_E_INVALID
+    assert call(1 << 12) == heom.HEOM_E_INVALID
