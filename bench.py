@@ -22,6 +22,40 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# rocprofv3 summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE traffic),
+# and the sources whose digest it records.
+PROFILE = os.path.join(ROOT, "profiles", "stage_tile_7_fp64_fmo_batch.md")
+KERNEL_SOURCES = ["paper_1012_4382_amd/csrc/stage_kernels.h",
+                  "paper_1012_4382_amd/csrc/heom_internal.h",
+                  "paper_1012_4382_amd/csrc/kernels_tile_7.hip", "paper_1012_4382_amd/build.py"]
+
+
+def _kernel_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _profiled_traffic(kernel: str):
+    """Counted HBM bytes per launch from the committed profile, or None when
+    the profile is of another kernel or of sources that have changed since."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    import re
+
+    k = re.search(r"^- kernel: `([^`]+)`", text, re.M)
+    d = re.search(r"^- source digest: `([0-9a-f]+)`", text, re.M)
+    t = re.search(r"^- traffic per launch \(bytes\): (\d+)", text, re.M)
+    if not (k and d and t) or k.group(1) != kernel or d.group(1) != _kernel_digest():
+        return None
+    return float(t.group(1))
 
 
 def _parse():
@@ -232,8 +266,11 @@ def main():
     # Launch shape the autotuner chose for this workload (during the warm-up).
     n_tiles = sum((h.n_ados + 63) // 64 for h in hs)
     shape, shape_us = heom.autotune_lookup(N, 1, n_tiles, "fp64")
+    kernel_name = {"auto": f"stage_tile<{N},1,double,{max(shape, 0)}>",
+                   "lane": f"stage_fixed<{N},1,double>",
+                   "generic": "stage_generic<double>"}[args.kernel]
     autotune = {"tiles": n_tiles, "shape": shape,
-                "first_stage_us_per_shape": [round(float(u), 3) for u in shape_us],
+                "stage_us_per_shape": [round(float(u), 3) for u in shape_us],
                 "shapes": [heom.tile_shape_info(N, 1, "fp64", k)
                            for k in range(heom.tile_shape_count())]}
 
@@ -255,10 +292,8 @@ def main():
                    "rk4_steps": steps_rk, "dt_fs": 1.0, "record_every": record_every,
                    "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": {"auto": f"stage_tile<{N},1,double,{max(shape, 0)}>",
-                                "lane": f"stage_fixed<{N},1,double>",
-                                "generic": "stage_generic<double>"}[args.kernel],
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _profiled_traffic(kernel_name),
+                     "kernel": kernel_name,
                      "kernel_avg_us": kernel_ms * 1e3, "bytes_per_launch": bytes_per_launch},
         "population_defect": defect,
         "autotune": autotune,

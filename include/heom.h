@@ -225,24 +225,27 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
  * first call that meets a new key (GPU architecture, precision, N, K + 1,
  * floor(log2(tiles))) - tiles being the 64-ADO blocks of all of the call's
  * instances with that N and K + 1 - times each distinct shape on its own
- * launch (repeated first RK4 stages, which leave the run unchanged), then
- * uses and remembers the fastest; later calls with that key reuse it.  If the
+ * launch (repeated sequences of RK4 stages 1, 2, 3, 2, which never write the
+ * state, so the run is unchanged), then uses and remembers the fastest;
+ * later calls with that key reuse it.  If the
  * environment variable HEOM_AUTOTUNE_CACHE names a file, entries are read
  * from it on first use and new ones are appended (one JSON object per line).
  *
  * heom_tile_shape_count: number of shape slots (shapes are 0 .. count-1).
  * heom_tile_shape_info: for N sites and K + 1 modes per site, the threads per
- *   workgroup, target elements per wave and load chunk of `shape`; any output
- *   may be NULL.  HEOM_E_UNSUPPORTED if the shape is not built for this N.
+ *   workgroup, target elements per wave, load chunk and minimum waves per
+ *   SIMD (register budget) of `shape`; any output may be NULL.
+ *   HEOM_E_UNSUPPORTED if the shape is not built for this N.
  * heom_autotune_lookup: the tuned shape for that key on the current device,
  *   or -1 if not tuned yet; us_per_shape [count] (or NULL) receives the
- *   measured microseconds per first-stage launch of each shape, -1 where a
- *   shape was not timed.
+ *   measured microseconds per stage launch of each shape, -1 where a shape
+ *   was not timed.
  * heom_autotune_clear: forgets every tuned entry of the process (entries in
  *   the cache file are read again on next use). */
 int heom_tile_shape_count(void);
 int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision, int32_t shape,
-                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk);
+                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk,
+                         int32_t *min_waves_per_simd);
 int heom_autotune_lookup(int32_t n_sites, int32_t modes_per_site, int precision, int64_t n_tiles,
                          int32_t *shape, double *us_per_shape);
 void heom_autotune_clear(void);

@@ -27,7 +27,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
 # (source, tile launch shape it is compiled for, or None).  The tile units of
 # N <= 8 are compiled once per shape (the autotuner's candidates); N = 9..12
 # in the default shape only.
-_SHAPES = 3
+_SHAPES = 5
 SOURCES = ([("params.cpp", None), ("hierarchy.cpp", None), ("runtime.cpp", None),
             ("autotune.cpp", None), ("kernels_dispatch.hip", None), ("kernels_lane.hip", None)] +
            [(f"kernels_tile_{u}.hip", s) for u in ("small", "7", "8") for s in range(_SHAPES)] +

@@ -1,8 +1,8 @@
 // autotune.cpp -- launch-shape autotuner of the tile stage kernel.
 //
 // The tile kernel is compiled in several launch shapes (waves per workgroup,
-// packed elements per wave, elements whose gathers are in flight together;
-// tile_shape in stage_kernels.h).  Which one is fastest depends on the size of
+// packed elements per wave, elements whose gathers are in flight together,
+// register budget; tile_shape in stage_kernels.h).  Which one is fastest depends on the size of
 // the launch: a launch of a few hundred tiles is latency-bound and prefers
 // long load batches, a launch of thousands of tiles is bandwidth-bound and
 // prefers shapes that keep more workgroups resident.  The tuner keys its
@@ -71,9 +71,31 @@ std::string arch_of(int device) {
   return name;
 }
 
-// One line of the cache file:
+// One line of the cache file (one timing per shape slot, -1 where untimed):
 // {"arch": "gfx950", "precision": 0, "N": 7, "KP": 1, "tiles_log2": 8, "shape": 1,
-//  "us": [10.6, 9.8, 12.0]}
+//  "us": [10.6, 9.8, 12.0, -1.0, 11.1]}
+bool parse_line(const char *line, Key *key, Entry *e) {
+  char arch[64] = {0};
+  int prec, N, KP, tl, shape, used = 0;
+  const int got = std::sscanf(line,
+                              " {\"arch\": \"%63[^\"]\", \"precision\": %d, \"N\": %d, \"KP\": %d, "
+                              "\"tiles_log2\": %d, \"shape\": %d, \"us\": [%n",
+                              arch, &prec, &N, &KP, &tl, &shape, &used);
+  if (got != 6 || used == 0 || shape < 0 || shape >= kMaxTileShapes) return false;
+  const char *p = line + used;
+  for (int s = 0; s < kMaxTileShapes; ++s) {
+    char *end = nullptr;
+    e->us[s] = std::strtod(p, &end);
+    if (end == p) return false;
+    p = end;
+    while (*p == ',' || *p == ' ') ++p;
+  }
+  if (*p != ']') return false;
+  e->shape = shape;
+  *key = Key(arch, prec, N, KP, tl);
+  return true;
+}
+
 void read_file_locked() {
   if (g_file_read) return;
   g_file_read = true;
@@ -81,21 +103,11 @@ void read_file_locked() {
   if (!path) return;
   FILE *f = std::fopen(path, "r");
   if (!f) return;
-  char line[512];
+  char line[1024];
   while (std::fgets(line, sizeof(line), f)) {
-    char arch[64] = {0};
-    int prec, N, KP, tl, shape;
-    double us[kMaxTileShapes];
-    for (double &u : us) u = -1.0;
-    const int got = std::sscanf(line,
-                                " {\"arch\": \"%63[^\"]\", \"precision\": %d, \"N\": %d, \"KP\": %d, "
-                                "\"tiles_log2\": %d, \"shape\": %d, \"us\": [%lf, %lf, %lf]",
-                                arch, &prec, &N, &KP, &tl, &shape, &us[0], &us[1], &us[2]);
-    if (got < 6 || shape < 0 || shape >= kMaxTileShapes) continue;  // not an entry
+    Key k;
     Entry e;
-    e.shape = shape;
-    for (int s = 0; s < kMaxTileShapes; ++s) e.us[s] = us[s];
-    g_cache[Key(arch, prec, N, KP, tl)] = e;
+    if (parse_line(line, &k, &e)) g_cache[k] = e;  // other lines are ignored
   }
   std::fclose(f);
 }
@@ -107,15 +119,16 @@ void append_file_locked(const Key &k, const Entry &e) {
   if (!f) return;  // the in-memory entry still holds
   std::fprintf(f,
                "{\"arch\": \"%s\", \"precision\": %d, \"N\": %d, \"KP\": %d, \"tiles_log2\": %d, "
-               "\"shape\": %d, \"us\": [%.3f, %.3f, %.3f]}\n",
+               "\"shape\": %d, \"us\": [",
                std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-               std::get<4>(k), e.shape, e.us[0], e.us[1], e.us[2]);
+               std::get<4>(k), e.shape);
+  for (int s = 0; s < kMaxTileShapes; ++s)
+    std::fprintf(f, s ? ", %.3f" : "%.3f", e.us[s]);
+  std::fprintf(f, "]}\n");
   std::fclose(f);
 }
 
 }  // namespace
-
-static_assert(kMaxTileShapes == 3, "the cache line format holds three timings");
 
 int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
                     const std::function<int(int, double *)> &time_shape, int *shape_out) {
@@ -133,17 +146,18 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
   // as an earlier one are the same kernel in effect and are skipped).
   Entry e;
   for (double &u : e.us) u = -1.0;
-  int seen_threads[kMaxTileShapes], seen_chunk[kMaxTileShapes], n_seen = 0;
+  int seen[kMaxTileShapes][3], n_seen = 0;
   double best = 0.0;
   for (int s = 0; s < kMaxTileShapes; ++s) {
-    int threads = 0, epw = 0, chunk = 0;
-    if (!tile_shape_info(N, KP, mixed, s, &threads, &epw, &chunk)) continue;
+    int threads = 0, epw = 0, chunk = 0, waves = 0;
+    if (!tile_shape_info(N, KP, mixed, s, &threads, &epw, &chunk, &waves)) continue;
     bool dup = false;
     for (int q = 0; q < n_seen; ++q)
-      dup = dup || (seen_threads[q] == threads && seen_chunk[q] == chunk);
+      dup = dup || (seen[q][0] == threads && seen[q][1] == chunk && seen[q][2] == waves);
     if (dup) continue;
-    seen_threads[n_seen] = threads;
-    seen_chunk[n_seen] = chunk;
+    seen[n_seen][0] = threads;
+    seen[n_seen][1] = chunk;
+    seen[n_seen][2] = waves;
     ++n_seen;
     double us = 0.0;
     int rc = time_shape(s, &us);

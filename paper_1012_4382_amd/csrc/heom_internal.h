@@ -90,7 +90,7 @@ struct InstDesc {
 enum class KernelKind { kTile, kLane, kGeneric };
 
 // Launch shapes of the tile kernel (the autotuner's candidates).
-constexpr int kMaxTileShapes = 3;
+constexpr int kMaxTileShapes = 5;
 
 // A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
 struct WorkItem {
@@ -139,7 +139,7 @@ int build_tables(heom_hierarchy *h);
 // kernels_dispatch.hip: whether the tile kernel exists for (N, K+1, storage)
 // in launch shape `shape`, and that shape's parameters.
 bool tile_shape_info(int N, int KP, bool mixed, int shape, int *threads, int *elems_per_wave,
-                     int *chunk);
+                     int *chunk, int *min_waves);
 // autotune.cpp: the launch shape of a tile group of n_tiles tiles, from the
 // cache or, for a new key, by timing each candidate with time_shape(shape,
 // &microseconds_per_launch).

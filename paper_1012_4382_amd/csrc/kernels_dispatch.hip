@@ -16,6 +16,12 @@ StageKernel tile_kernel_part_7_s2(int, int, bool);
 StageKernel tile_kernel_part_8_s0(int, int, bool);
 StageKernel tile_kernel_part_8_s1(int, int, bool);
 StageKernel tile_kernel_part_8_s2(int, int, bool);
+StageKernel tile_kernel_part_small_s3(int, int, bool);
+StageKernel tile_kernel_part_7_s3(int, int, bool);
+StageKernel tile_kernel_part_8_s3(int, int, bool);
+StageKernel tile_kernel_part_small_s4(int, int, bool);
+StageKernel tile_kernel_part_7_s4(int, int, bool);
+StageKernel tile_kernel_part_8_s4(int, int, bool);
 StageKernel tile_kernel_part_9_10_s0(int, int, bool);
 StageKernel tile_kernel_part_11_s0(int, int, bool);
 StageKernel tile_kernel_part_12_s0(int, int, bool);
@@ -23,13 +29,17 @@ StageKernel lane_kernel_ptr(int N, int KP, bool mixed);
 
 namespace {
 
-static_assert(kTileShapes == 3, "one row of tile parts per shape");
+static_assert(kTileShapes == 5, "one row of tile parts per shape");
 constexpr TilePart kTileParts[kTileShapes][6] = {
     {&tile_kernel_part_small_s0, &tile_kernel_part_7_s0, &tile_kernel_part_8_s0,
      &tile_kernel_part_9_10_s0, &tile_kernel_part_11_s0, &tile_kernel_part_12_s0},
     {&tile_kernel_part_small_s1, &tile_kernel_part_7_s1, &tile_kernel_part_8_s1, nullptr, nullptr,
      nullptr},
     {&tile_kernel_part_small_s2, &tile_kernel_part_7_s2, &tile_kernel_part_8_s2, nullptr, nullptr,
+     nullptr},
+    {&tile_kernel_part_small_s3, &tile_kernel_part_7_s3, &tile_kernel_part_8_s3, nullptr, nullptr,
+     nullptr},
+    {&tile_kernel_part_small_s4, &tile_kernel_part_7_s4, &tile_kernel_part_8_s4, nullptr, nullptr,
      nullptr},
 };
 
@@ -49,12 +59,13 @@ bool has_fixed_kernel(int N, int KP) { return lane_kernel_ptr(N, KP, false) != n
 bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false, 0) != nullptr; }
 
 bool tile_shape_info(int N, int KP, bool mixed, int shape, int *threads, int *elems_per_wave,
-                     int *chunk) {
+                     int *chunk, int *min_waves) {
   if (!tile_kernel(N, KP, mixed, shape)) return false;
   const TileShape sh = tile_shape(!mixed, shape);
   if (threads) *threads = 64 * tile_waves(N, !mixed, shape);
   if (elems_per_wave) *elems_per_wave = sh.elems_per_wave;
   if (chunk) *chunk = sh.chunk;
+  if (min_waves) *min_waves = sh.min_waves;
   return true;
 }
 

@@ -272,8 +272,8 @@ struct Group {
   int64_t item_begin, n_items, n_tiles;  // n_tiles: items that are not padding
 };
 
-// First-stage launches timed per candidate shape by the autotuner (after one
-// untimed launch).
+// Stage sequences timed per candidate shape by the autotuner (after one
+// untimed sequence).
 constexpr int kTuneReps = 5;
 
 // Tile launch shape forced by the flags (HEOM_TILE_SHAPE(s)), or -1.
@@ -315,8 +315,9 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
     for (int k = 0; k < n; ++k) {
       const heom_hierarchy *h = hs[k];
       const bool mixed = precision == HEOM_FP32_MIXED;
-      if (h->h_real && tile_shape_info(h->N, h->KP, mixed, 0, nullptr, nullptr, nullptr) &&
-          !tile_shape_info(h->N, h->KP, mixed, forced, nullptr, nullptr, nullptr))
+      const bool tiled = tile_shape_info(h->N, h->KP, mixed, 0, nullptr, nullptr, nullptr, nullptr);
+      if (h->h_real && tiled &&
+          !tile_shape_info(h->N, h->KP, mixed, forced, nullptr, nullptr, nullptr, nullptr))
         return fail(HEOM_E_UNSUPPORTED, "tile launch shape " + std::to_string(forced) +
                                             " is not built for N=" + std::to_string(h->N) +
                                             ", K+1=" + std::to_string(h->KP));
@@ -410,7 +411,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     g.shape = 0;
     if (g.kind == KernelKind::kTile) {
       g.ados_per_item = 64;
-      if (!tile_shape_info(g.N, g.KP, mixed, 0, &g.threads, nullptr, nullptr))
+      if (!tile_shape_info(g.N, g.KP, mixed, 0, &g.threads, nullptr, nullptr, nullptr))
         return fail(HEOM_E_UNSUPPORTED, "no tile kernel for this hierarchy");
     } else {
       g.ados_per_item = block_ados();
@@ -521,8 +522,10 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   }
   const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
   // Launch shape of each tile group: forced by the flags, the default, or
-  // the autotuner's.  The tuner times repeated first stages, which read the
-  // state and write only the first stage buffer, so the run is unchanged.
+  // the autotuner's.  The tuner times repeated stage sequences 1, 2, 3, 2:
+  // the same traffic as a step, but none of them writes the state y (only
+  // the last stage does), and the run's first step rewrites the stage
+  // buffers they leave behind before reading them, so the run is unchanged.
   for (Group &g : groups) {
     if (g.kind != KernelKind::kTile) continue;
     int shape = forced_shape(flags);  // validated when the groups were formed
@@ -530,18 +533,22 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     if (shape < 0) {
       auto time_shape = [&](int s, double *us) -> int {
         int threads = 0;
-        tile_shape_info(g.N, g.KP, mixed, s, &threads, nullptr, nullptr);
+        tile_shape_info(g.N, g.KP, mixed, s, &threads, nullptr, nullptr, nullptr);
         hipEvent_t ev[2] = {nullptr, nullptr};
         int rc = HEOM_OK;
-        auto launch = [&]() {
-          return launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.item_begin,
-                              static_cast<int>(g.n_items), threads, 0, coef[0], -1, stream);
+        auto pseudo_step = [&]() {
+          hipError_t e = hipSuccess;
+          for (int st : {0, 1, 2, 1})
+            if (e == hipSuccess)
+              e = launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.item_begin,
+                               static_cast<int>(g.n_items), threads, st, coef[st], -1, stream);
+          return e;
         };
         hipError_t e = hipEventCreate(&ev[0]);
         if (e == hipSuccess) e = hipEventCreate(&ev[1]);
-        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = pseudo_step();
         if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
-        for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = launch();
+        for (int r = 0; r < kTuneReps && e == hipSuccess; ++r) e = pseudo_step();
         if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
         float ms = 0.0f;
@@ -549,14 +556,14 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
         if (e != hipSuccess) rc = dev_fail(e, "autotune timing");
         for (hipEvent_t x : ev)
           if (x) (void)hipEventDestroy(x);
-        *us = 1000.0 * static_cast<double>(ms) / kTuneReps;
+        *us = 1000.0 * static_cast<double>(ms) / (4 * kTuneReps);
         return rc;
       };
       int rc = autotune_choose(device, mixed, g.N, g.KP, g.n_tiles, time_shape, &shape);
       if (rc) return rc;
     }
     g.shape = shape;
-    tile_shape_info(g.N, g.KP, mixed, shape, &g.threads, nullptr, nullptr);
+    tile_shape_info(g.N, g.KP, mixed, shape, &g.threads, nullptr, nullptr, nullptr);
   }
   // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.
   auto enqueue_step = [&](hipStream_t s) -> hipError_t {
@@ -981,16 +988,19 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
 int heom_tile_shape_count(void) { return kMaxTileShapes; }
 
 int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision, int32_t shape,
-                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk) {
+                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk,
+                         int32_t *min_waves_per_simd) {
   if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
     return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
   if (shape < 0 || shape >= kMaxTileShapes) return fail(HEOM_E_INVALID, "shape out of range");
-  int t = 0, e = 0, c = 0;
-  if (!tile_shape_info(n_sites, modes_per_site, precision == HEOM_FP32_MIXED, shape, &t, &e, &c))
+  int t = 0, e = 0, c = 0, w = 0;
+  if (!tile_shape_info(n_sites, modes_per_site, precision == HEOM_FP32_MIXED, shape, &t, &e, &c,
+                       &w))
     return fail(HEOM_E_UNSUPPORTED, "the tile kernel is not built for this N, K+1 and shape");
   if (threads) *threads = t;
   if (elems_per_wave) *elems_per_wave = e;
   if (chunk) *chunk = c;
+  if (min_waves_per_simd) *min_waves_per_simd = w;
   return HEOM_OK;
 }
 

@@ -522,12 +522,6 @@ __global__ void __launch_bounds__(256) stage_generic(const InstDesc *__restrict_
 
 constexpr int kTile = 64;
 
-// Minimum waves per SIMD requested from the register allocator for the tile
-// kernel (trades registers for resident waves).
-#ifndef HEOM_TILE_MIN_WAVES_PER_SIMD
-#define HEOM_TILE_MIN_WAVES_PER_SIMD 1
-#endif
-
 // Packed element p -> (a, b), a <= b: p < N are the diagonal entries, then
 // the pairs a < b in row-major order.
 __host__ __device__ constexpr int elem_a(int N, int p) {
@@ -560,19 +554,22 @@ __host__ __device__ constexpr int ent_sg(int r, int c) { return r > c ? -1 : 1; 
 
 // Launch shapes of the tile kernel, the candidates of the autotuner: the
 // target number of packed elements per wave (which sets the waves per
-// workgroup, see tile_waves_for) and how many of a wave's elements have their
-// global loads in flight together (one chunk).  Shape 0 is the default:
-// measured on the FMO-shaped 7-site workloads, FP64 does best with fewer,
-// longer waves and short load chunks, FP32 with more waves and longer chunks.
-// Every shape computes each element with the same instructions in the same
-// order, so the results do not depend on the shape.
+// workgroup, see tile_waves_for), how many of a wave's elements have their
+// global loads in flight together (one chunk), and the minimum waves per SIMD
+// asked of the register allocator (7 caps a wave at 72 VGPRs, so that two
+// 14-wave workgroups fit on a CU).  Small launches are latency-bound and
+// prefer few load round trips with every workgroup resident; large ones are
+// bandwidth-bound.  Shape 0 is the default (HEOM_NO_AUTOTUNE).  Every shape
+// computes each element with the same instructions in the same order, so the
+// results do not depend on the shape.
 struct TileShape {
-  int elems_per_wave, chunk;
+  int elems_per_wave, chunk, min_waves;
 };
 constexpr int kTileShapes = kMaxTileShapes;
+constexpr TileShape kShapesF64[kTileShapes] = {{7, 2, 1}, {7, 7, 1}, {2, 2, 1}, {4, 2, 1}, {2, 1, 7}};
+constexpr TileShape kShapesF32[kTileShapes] = {{4, 4, 1}, {4, 2, 1}, {2, 2, 1}, {7, 2, 1}, {2, 1, 7}};
 __host__ __device__ constexpr TileShape tile_shape(bool fp64, int s) {
-  return fp64 ? (s == 0 ? TileShape{7, 2} : s == 1 ? TileShape{7, 7} : TileShape{2, 2})
-              : (s == 0 ? TileShape{4, 4} : s == 1 ? TileShape{4, 2} : TileShape{2, 2});
+  return fp64 ? kShapesF64[s] : kShapesF32[s];
 }
 #ifndef HEOM_TILE_CHUNK_BARRIER
 #define HEOM_TILE_CHUNK_BARRIER 1
@@ -798,7 +795,7 @@ __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
 
 template <int N, int KP, typename T, int SHAPE>
 __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
-                                  HEOM_TILE_MIN_WAVES_PER_SIMD)
+                                  tile_shape(sizeof(T) == 8, SHAPE).min_waves)
     stage_tile(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
                double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
   constexpr int N2 = N * N;

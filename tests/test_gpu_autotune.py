@@ -2,8 +2,8 @@
 
 Every shape computes each packed element with the same instructions, so the
 results must be bitwise identical across shapes; the autotuner times repeated
-first RK4 stages on the caller's own launch, which must leave the run
-unchanged.  Parity of the default path with the FP64 oracle is covered by
+sequences of RK4 stages that never write the state, on the caller's own
+launch, which must leave the run unchanged.  Parity of the default path with the FP64 oracle is covered by
 test_gpu_parity.py; one case here also checks a forced shape against it.
 """
 import json
@@ -105,7 +105,7 @@ def test_autotuner_choice_is_cached_and_leaves_the_run_unchanged(precision):
     assert 0 <= shape < heom.tile_shape_count()
     timed = us[us >= 0]
     assert len(timed) >= 2 and np.all(timed > 0) and us[shape] == np.min(timed)
-    _say(f"  tuned shape {shape}, us per first stage {us.tolist()}")
+    _say(f"  tuned shape {shape}, us per stage launch {us.tolist()}")
     plain, s_plain, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5,
                                              precision=precision, autotune=False)
     for a, b in zip(tuned, plain):

@@ -178,7 +178,7 @@ def test_tile_shapes_and_forced_shape_validation():
     shape that is out of range or not built is rejected before device work."""
     lib = heom.library()
     count = heom.tile_shape_count()
-    assert count == 3
+    assert count == 5
     for N in range(1, 13):
         P = N * (N + 1) // 2
         for prec in ("fp64", "fp32"):
@@ -187,12 +187,13 @@ def test_tile_shapes_and_forced_shape_validation():
                 if s == 0 or N <= 8:
                     assert info is not None, (N, prec, s)
                 if info is not None:
-                    threads, epw, chunk = info
+                    threads, epw, chunk, waves = info
                     assert threads % 64 == 0 and 64 <= threads <= 1024
                     assert P % (threads // 64) == 0 and epw >= 1 and chunk >= 1
+                    assert 1 <= waves <= 8
     assert heom.tile_shape_info(13, 1, "fp64", 0) is None
-    assert lib.heom_tile_shape_info(7, 1, 0, count, None, None, None) == heom.HEOM_E_INVALID
-    assert lib.heom_tile_shape_info(7, 1, 5, 0, None, None, None) == heom.HEOM_E_UNSUPPORTED
+    assert lib.heom_tile_shape_info(7, 1, 0, count, None, None, None, None) == heom.HEOM_E_INVALID
+    assert lib.heom_tile_shape_info(7, 1, 5, 0, None, None, None, None) == heom.HEOM_E_UNSUPPORTED
 
     H = np.diag(np.linspace(12300.0, 12500.0, 12)) + np.diag(np.full(11, -80.0), 1) \
         + np.diag(np.full(11, -80.0), -1)
