@@ -74,8 +74,10 @@ def _parse():
                    help="also run a plain 256 MiB device copy (reference for traffic counters)")
     p.add_argument("--no-sweep", action="store_true",
                    help="skip the 64-instance parameter-sweep measurement")
-    p.add_argument("--serve", type=int, default=0, metavar="R",
-                   help="also serve the first R requests of the serving trace (0: skip)")
+    p.add_argument("--serve", type=int, default=40, metavar="R",
+                   help="serve the first R requests of the serving trace (0: skip)")
+    p.add_argument("--serve-precision", default="fp64", choices=["fp64", "fp32"],
+                   help="storage precision of the served solves")
     return p.parse_args()
 
 
@@ -135,29 +137,55 @@ def _precision(heom, workloads, stream):
             "max_rel_p_trap_error": float(np.max(dtrap / ptrap)), "bar": 1e-5}
 
 
-def _serve(heom, workloads, stream, n_requests):
+def _serve(heom, workloads, stream, n_requests, precision="fp64"):
     """The first n_requests of the serving trace (Poisson arrivals, mean 50 ms;
     N in {2,7,8,12,24}, depth 2-4, 2-10 ps), served by the continuous-batching
-    engine in real time, then the same requests one at a time (FIFO)."""
+    engine in real time, then the same requests one at a time (FIFO).  A sample
+    of the served results is checked against the same solves run alone in
+    FP64 (bitwise for FP64 serving, within 1e-5 for FP32-mixed)."""
     from paper_1012_4382_amd.serve import Engine, GpuBackend, Request
 
     def reqs():
         return [Request(id=w["id"], system=w["system"], depth=w["depth"], rho0=w["rho0"],
-                        steps=w["steps"], arrival_s=w["arrival_s"])
+                        steps=w["steps"], arrival_s=w["arrival_s"], precision=precision)
                 for w in workloads.serving_trace(n_requests)]
+
+    def progress(tag):
+        count = [0]
+
+        def on_finish(r):
+            count[0] += 1
+            if count[0] % 10 == 0 or count[0] == n_requests:
+                print(f"serve {tag} {precision}: {count[0]}/{n_requests} finished",
+                      file=sys.stderr, flush=True)
+        return on_finish
 
     import torch
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * 0.9)
     eng = Engine(GpuBackend(stream=stream), hbm_budget_bytes=budget, chunk_steps=200)
-    m = eng.run(reqs())
-    fifo = Engine(GpuBackend(stream=stream), hbm_budget_bytes=budget, chunk_steps=200)
-    fifo_reqs = reqs()
-    # One at a time: admission budget of one request's footprint.
-    fifo.budget = max(fifo.backend.footprint(r)[0] for r in fifo_reqs)
-    mf = fifo.run(fifo_reqs)
-    return {"requests": n_requests, "budget_bytes": budget, "continuous_batching": m,
-            "fifo_one_at_a_time": mf}
+    served = reqs()
+    m = eng.run(served, on_finish=progress("batched"))
+    fifo = Engine(GpuBackend(stream=stream), hbm_budget_bytes=budget, chunk_steps=200,
+                  max_active=1)
+    mf = fifo.run(reqs(), on_finish=progress("fifo"))
+    # Check: up to 8 served solves (of at most 2e7 ADO-steps each) against the
+    # same solve alone in FP64.
+    sample = [r for r in served if r.status == "done" and r.n_ados * r.steps <= 2e7][:8]
+    dp, dtrap, bitwise = 0.0, 0.0, True
+    for r in sample:
+        h = heom.Hierarchy(r.system, r.depth)
+        rho, sinks, _ = heom.propagate(h, r.rho0, r.dt, r.steps, record_every=r.steps,
+                                       stream=stream)
+        ref = rho[-1]
+        dp = max(dp, float(np.max(np.abs(np.real(np.diag(r.rho_final)) - np.real(np.diag(ref))))))
+        dtrap = max(dtrap, abs(float(r.sinks[0]) - float(sinks[0])))
+        bitwise = bitwise and np.array_equal(r.rho_final, ref) and np.array_equal(r.sinks, sinks)
+    return {"requests": n_requests, "precision": precision, "budget_bytes": budget,
+            "continuous_batching": m, "fifo_one_at_a_time": mf,
+            "check_vs_fp64_alone": {"sample": [r.id for r in sample],
+                                    "max_abs_pop_error": dp, "max_abs_p_trap_error": dtrap,
+                                    "bitwise_equal": bool(bitwise), "bar": 1e-5}}
 
 
 def _stage_kernel_timing(heom, torch, hs, rho0s, stream, kernel, precision="fp64", steps=500):
@@ -183,6 +211,25 @@ def _sizing(heom, torch, workloads, stream, kernel):
     w = workloads.fmo_like(seed=0, site=1, depth=16, steps=200)
     h = heom.Hierarchy(w["system"], w["depth"])
     out = {"workload": "fmo_like_7site_depth16_single_solve", "n_ados": h.n_ados}
+    for prec, s in (("fp64", 8), ("fp32", 4)):
+        k_ms, rate = _stage_kernel_timing(heom, torch, [h], [w["rho0"]], stream, kernel, prec,
+                                          steps=100)
+        bpl = h.n_ados * (11.0 / 4.0) * h.N * h.N * s
+        out[prec] = {"ado_steps_per_s": rate, "kernel_avg_us": k_ms * 1e3,
+                     "achieved_GBps": bpl / (k_ms * 1e-3) / 1e9,
+                     "frac_of_hbm_peak": bpl / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
+def _wide_sizing(heom, torch, workloads, stream, kernel):
+    """The serving workload's largest shape: a 24-site chain or ring at depth 4
+    (20475 ADOs), one solve, FP64 and FP32-mixed, on the LDS-tiled kernels
+    (the autotuner's pick; for N = 24 only the 16-ADO wide kernel exists)."""
+    w = next(r for r in workloads.serving_trace(200)
+             if r["system"]["H"].shape[0] == 24 and r["depth"] == 4)
+    h = heom.Hierarchy(w["system"], w["depth"])
+    out = {"workload": f"serving_24site_{w['topology']}_depth4_single_solve",
+           "n_ados": h.n_ados}
     for prec, s in (("fp64", 8), ("fp32", 4)):
         k_ms, rate = _stage_kernel_timing(heom, torch, [h], [w["rho0"]], stream, kernel, prec,
                                           steps=100)
@@ -319,12 +366,13 @@ def main():
                               "fp64_batched_over_single": value / plain}
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
+        result["wide_sizing"] = _wide_sizing(heom, torch, workloads, stream, args.kernel)
     if not args.no_sweep:
         result["sweep"] = _sweep(heom, torch, workloads, stream)
     if not args.no_variants:
         result["precision"] = _precision(heom, workloads, stream)
     if args.serve > 0:
-        result["serving"] = _serve(heom, workloads, stream, args.serve)
+        result["serving"] = _serve(heom, workloads, stream, args.serve, args.serve_precision)
     if args.copy_calibration:
         # A plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
         # kernel calibrate the traffic counters of the stage kernel.

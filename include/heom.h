@@ -63,8 +63,8 @@ enum {
                                kernel instead of the LDS-tiled one (N <= 8)     */
   HEOM_NO_GRAPH = 8,        /* diagnostic: launch every stage kernel directly
                                instead of replaying captured graphs of steps    */
-  HEOM_NO_AUTOTUNE = 16     /* use tile launch shape 0 instead of the
-                               autotuned one                                    */
+  HEOM_NO_AUTOTUNE = 16     /* use the default launch shape of the LDS-tiled
+                               kernels instead of the autotuned one             */
 };
 /* Flag bits that force tile launch shape s (0 <= s < heom_tile_shape_count())
  * for every tile-kernel group of a call. */
@@ -213,29 +213,32 @@ int heom_efficiency(heom_hierarchy *h, int precision, const double *rho0, double
 int heom_read_state(const heom_hierarchy *h, int precision, const void *d_workspace,
                     size_t workspace_bytes, void *hip_stream, double *state_out);
 
-/* Launch shapes of the tile stage kernel and their autotuner.
+/* Launch shapes of the LDS-tiled stage kernels and their autotuner.
  *
- * The stage kernel for real H and N <= 12 stages 64 consecutive ADOs per
- * workgroup in LDS (the paper's blocking of ADOs per thread block, Appendix B,
- * redone for wave64 and LDS).  It is built in several launch shapes, which
- * differ in the waves per workgroup, the packed elements each wave computes
- * and how many elements have their neighbour gathers in flight together;
- * every shape performs the same arithmetic, so results do not depend on the
- * shape.  Unless a call passes HEOM_NO_AUTOTUNE or HEOM_TILE_SHAPE(s), the
- * first call that meets a new key (GPU architecture, precision, N, K + 1,
- * floor(log2(tiles))) - tiles being the 64-ADO blocks of all of the call's
- * instances with that N and K + 1 - times each distinct shape on its own
- * launch (repeated sequences of RK4 stages 1, 2, 3, 2, which never write the
- * state, so the run is unchanged), then uses and remembers the fastest;
- * later calls with that key reuse it.  If the
+ * For real H the stage runs in an LDS-tiled kernel: a workgroup stages a block
+ * of consecutive ADOs with the Hamiltonian and their neighbour tables in LDS
+ * (the paper's blocking of ADOs per thread block, Appendix B, redone for
+ * wave64 and LDS).  Shapes 0-4 are the 64-ADO tile kernel (N <= 12), which
+ * differ in the waves per workgroup, the packed elements each wave computes,
+ * how many elements have their neighbour gathers in flight together and the
+ * register budget.  Shape 5 is the 16-ADO wide kernel (N <= 32 while its LDS
+ * fits: all N <= 32 for K + 1 <= 4).  Every shape computes each element with
+ * the same operations, so results do not depend on the shape.  Unless a call
+ * passes HEOM_NO_AUTOTUNE (then shape 0, or 5 where 0 is not built) or
+ * HEOM_TILE_SHAPE(s), the first call that meets a new key (GPU architecture,
+ * precision, N, K + 1, floor(log2(tiles))) - tiles being the 64-ADO blocks of
+ * all of the call's instances with that N and K + 1 - times each distinct
+ * available shape on its own launch (repeated sequences of RK4 stages 1, 2,
+ * 3, 2, which never write the state, so the run is unchanged), then uses and
+ * remembers the fastest; later calls with that key reuse it.  If the
  * environment variable HEOM_AUTOTUNE_CACHE names a file, entries are read
  * from it on first use and new ones are appended (one JSON object per line).
  *
  * heom_tile_shape_count: number of shape slots (shapes are 0 .. count-1).
- * heom_tile_shape_info: for N sites and K + 1 modes per site, the threads per
- *   workgroup, target elements per wave, load chunk and minimum waves per
- *   SIMD (register budget) of `shape`; any output may be NULL.
- *   HEOM_E_UNSUPPORTED if the shape is not built for this N.
+ * heom_tile_shape_info: for N sites and K + 1 modes per site, the ADOs per
+ *   workgroup, threads per workgroup, packed elements per wave, load chunk
+ *   and minimum waves per SIMD (register budget) of `shape`; any output may
+ *   be NULL.  HEOM_E_UNSUPPORTED if the shape is not built for this N.
  * heom_autotune_lookup: the tuned shape for that key on the current device,
  *   or -1 if not tuned yet; us_per_shape [count] (or NULL) receives the
  *   measured microseconds per stage launch of each shape, -1 where a shape
@@ -244,8 +247,8 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
  *   the cache file are read again on next use). */
 int heom_tile_shape_count(void);
 int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision, int32_t shape,
-                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk,
-                         int32_t *min_waves_per_simd);
+                         int32_t *ados_per_workgroup, int32_t *threads, int32_t *elems_per_wave,
+                         int32_t *chunk, int32_t *min_waves_per_simd);
 int heom_autotune_lookup(int32_t n_sites, int32_t modes_per_site, int precision, int64_t n_tiles,
                          int32_t *shape, double *us_per_shape);
 void heom_autotune_clear(void);

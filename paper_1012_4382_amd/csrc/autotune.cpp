@@ -146,19 +146,31 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
   // as an earlier one are the same kernel in effect and are skipped).
   Entry e;
   for (double &u : e.us) u = -1.0;
-  int seen[kMaxTileShapes][3], n_seen = 0;
-  double best = 0.0;
+  int seen[kMaxTileShapes][4], n_seen = 0;
+  int cand[kMaxTileShapes], n_cand = 0;
   for (int s = 0; s < kMaxTileShapes; ++s) {
-    int threads = 0, epw = 0, chunk = 0, waves = 0;
-    if (!tile_shape_info(N, KP, mixed, s, &threads, &epw, &chunk, &waves)) continue;
+    int ados = 0, threads = 0, epw = 0, chunk = 0, waves = 0;
+    if (!tile_shape_info(N, KP, mixed, s, &ados, &threads, &epw, &chunk, &waves)) continue;
     bool dup = false;
     for (int q = 0; q < n_seen; ++q)
-      dup = dup || (seen[q][0] == threads && seen[q][1] == chunk && seen[q][2] == waves);
+      dup = dup || (seen[q][0] == ados && seen[q][1] == threads && seen[q][2] == chunk &&
+                    seen[q][3] == waves);
     if (dup) continue;
-    seen[n_seen][0] = threads;
-    seen[n_seen][1] = chunk;
-    seen[n_seen][2] = waves;
+    seen[n_seen][0] = ados;
+    seen[n_seen][1] = threads;
+    seen[n_seen][2] = chunk;
+    seen[n_seen][3] = waves;
     ++n_seen;
+    cand[n_cand++] = s;
+  }
+  if (n_cand == 0) return fail(HEOM_E_UNSUPPORTED, "no tile launch shape for this hierarchy");
+  if (n_cand == 1) {  // nothing to choose
+    *shape_out = cand[0];
+    return HEOM_OK;
+  }
+  double best = 0.0;
+  for (int q = 0; q < n_cand; ++q) {
+    const int s = cand[q];
     double us = 0.0;
     int rc = time_shape(s, &us);
     if (rc) return rc;

@@ -83,14 +83,17 @@ struct InstDesc {
 };
 
 // Stage kernel variants.
-//  kTile:    N <= 8, real H; 64 ADOs per workgroup staged in LDS, one packed
-//            element per wave (default where available)
+//  kTile:    real H, N <= 32; ADO tiles staged in LDS, in one of the launch
+//            shapes below (default where built)
 //  kLane:    N <= 8, real H; one lane per ADO, ADO held in registers
 //  kGeneric: any N, complex H; one lane per ADO, reads from the planes
 enum class KernelKind { kTile, kLane, kGeneric };
 
-// Launch shapes of the tile kernel (the autotuner's candidates).
-constexpr int kMaxTileShapes = 5;
+// Launch shapes of the LDS-tiled kernels, the autotuner's candidates:
+// shapes 0 .. kWideShape - 1 are the 64-ADO tile kernel (N <= 12), shape
+// kWideShape the 16-ADO wide kernel (N <= 32, LDS permitting).
+constexpr int kWideShape = 5;
+constexpr int kMaxTileShapes = kWideShape + 1;
 
 // A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
 struct WorkItem {
@@ -136,10 +139,11 @@ int fail(int status, const std::string &msg);
 int build_params(const heom_system *sys, heom_hierarchy *h);
 // hierarchy.cpp
 int build_tables(heom_hierarchy *h);
-// kernels_dispatch.hip: whether the tile kernel exists for (N, K+1, storage)
-// in launch shape `shape`, and that shape's parameters.
-bool tile_shape_info(int N, int KP, bool mixed, int shape, int *threads, int *elems_per_wave,
-                     int *chunk, int *min_waves);
+// kernels_dispatch.hip: whether launch shape `shape` exists for (N, K+1,
+// storage), and its ADOs per work item, threads per workgroup, elements per
+// wave, load chunk and minimum waves per SIMD (any output may be NULL).
+bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threads,
+                     int *elems_per_wave, int *chunk, int *min_waves);
 // autotune.cpp: the launch shape of a tile group of n_tiles tiles, from the
 // cache or, for a new key, by timing each candidate with time_shape(shape,
 // &microseconds_per_launch).

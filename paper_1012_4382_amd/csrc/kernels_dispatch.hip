@@ -58,20 +58,63 @@ bool has_fixed_kernel(int N, int KP) { return lane_kernel_ptr(N, KP, false) != n
 
 bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false, 0) != nullptr; }
 
-bool tile_shape_info(int N, int KP, bool mixed, int shape, int *threads, int *elems_per_wave,
-                     int *chunk, int *min_waves) {
-  if (!tile_kernel(N, KP, mixed, shape)) return false;
-  const TileShape sh = tile_shape(!mixed, shape);
-  if (threads) *threads = 64 * tile_waves(N, !mixed, shape);
-  if (elems_per_wave) *elems_per_wave = sh.elems_per_wave;
-  if (chunk) *chunk = sh.chunk;
-  if (min_waves) *min_waves = sh.min_waves;
+// The wide kernel's LDS (tile, Hamiltonian, tables) must fit the 160 KB of a
+// gfx950 CU.
+bool has_wide_kernel(int N, int M, bool mixed) {
+  constexpr int kLdsBytes = 160 * 1024;
+  return N >= 1 && N <= kWideMaxN && wide_lds(N, M, mixed ? 4 : 8).total <= kLdsBytes;
+}
+
+bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threads,
+                     int *elems_per_wave, int *chunk, int *min_waves) {
+  int a, t, e, c, w;
+  if (shape == kWideShape) {
+    if (!has_wide_kernel(N, N * KP, mixed)) return false;
+    const int P = N * (N + 1) / 2;
+    a = kWideAdos;
+    t = 64 * kWideWaves;
+    e = (P + kWideSlots - 1) / kWideSlots * (64 / kWideAdos);  // per wave, per ADO of the tile
+    c = 1;
+    w = 1;
+  } else {
+    if (!tile_kernel(N, KP, mixed, shape)) return false;
+    const TileShape sh = tile_shape(!mixed, shape);
+    a = kTile;
+    t = 64 * tile_waves(N, !mixed, shape);
+    e = sh.elems_per_wave;
+    c = sh.chunk;
+    w = sh.min_waves;
+  }
+  if (ados) *ados = a;
+  if (threads) *threads = t;
+  if (elems_per_wave) *elems_per_wave = e;
+  if (chunk) *chunk = c;
+  if (min_waves) *min_waves = w;
   return true;
+}
+
+// Dynamic LDS beyond the default limit has to be allowed per kernel; done
+// once per configuration before any launch (and before graph capture).
+hipError_t prepare_wide(int N, int M, bool mixed) {
+  const int bytes = wide_lds(N, M, mixed ? 4 : 8).total;
+  const void *k = mixed ? reinterpret_cast<const void *>(&stage_wide<float>)
+                        : reinterpret_cast<const void *>(&stage_wide<double>);
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
                         int stage, double coef, int hist_slot, hipStream_t stream) {
+  if (kind == KernelKind::kTile && shape == kWideShape) {
+    const size_t lds = static_cast<size_t>(wide_lds(N, N * KP, mixed ? 4 : 8).total);
+    if (mixed)
+      hipLaunchKernelGGL(stage_wide<float>, dim3(n_items), dim3(block), lds, stream, descs, work,
+                         stage, coef, hist_slot);
+    else
+      hipLaunchKernelGGL(stage_wide<double>, dim3(n_items), dim3(block), lds, stream, descs, work,
+                         stage, coef, hist_slot);
+    return hipGetLastError();
+  }
   StageKernel k = nullptr;
   switch (kind) {
     case KernelKind::kTile:

@@ -24,7 +24,7 @@ namespace heom {
 
 // stage_kernels.hip
 bool has_fixed_kernel(int N, int KP);
-bool has_tile_kernel(int N, int KP);
+hipError_t prepare_wide(int N, int M, bool mixed);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
                         int stage, double coef, int hist_slot, hipStream_t stream);
@@ -81,6 +81,14 @@ struct Layout {
   size_t total = 0;
 };
 
+// Work-list entries an instance of n_ados ADOs can need: its stage items in
+// 16-ADO and in 64-ADO tiles (a group may carry both lists), its
+// initialisation items (one per 64 ADOs) and the padding of each list to a
+// multiple of the XCD count.
+int64_t work_items_cap(int64_t n_ados) {
+  return (n_ados + 15) / 16 + 2 * ((n_ados + kPlanePad - 1) / kPlanePad) + 16;
+}
+
 Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   Layout L;
   size_t off = 0;
@@ -88,11 +96,8 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   off = align_up(off + sizeof(Header));
   L.descs = off;
   off = align_up(off + sizeof(InstDesc) * n);
-  // Work items: stage items (at most one per 64 ADOs) and initialisation
-  // items (one per 64 ADOs).
   int64_t cap = 0;
-  // (+8 per instance: padding of a kernel group to a multiple of the XCD count)
-  for (int k = 0; k < n; ++k) cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad) + 8;
+  for (int k = 0; k < n; ++k) cap += work_items_cap(hs[k]->n_ados);
   L.work = off;
   L.work_cap = cap;
   off = align_up(off + sizeof(WorkItem) * cap);
@@ -264,13 +269,25 @@ struct StepGraph {
   }
 };
 
+// The instances of one launch per stage.  A kTile group carries a work list
+// for each item size its launch shapes use (64-ADO tiles, 16-ADO wide tiles);
+// the chosen shape selects one.
 struct Group {
   KernelKind kind;
   int N, KP;
-  int shape;  // tile launch shape (kTile only)
-  int ados_per_item, threads;
-  int64_t item_begin, n_items, n_tiles;  // n_tiles: items that are not padding
+  int shape;    // launch shape (kTile only)
+  int threads;  // of the chosen shape
+  int64_t n_tiles;  // 64-ADO tiles of the group (the autotuner's size key)
+  int64_t begin[2] = {0, 0}, count[2] = {0, 0};  // work lists: [0] 64-ADO, [1] 16-ADO items
+  int list(int s) const { return (kind == KernelKind::kTile && s == kWideShape) ? 1 : 0; }
 };
+
+// Whether (N, K+1, storage) has any LDS-tiled launch shape.
+bool has_tiled(int N, int KP, bool mixed) {
+  for (int s = 0; s < kMaxTileShapes; ++s)
+    if (tile_shape_info(N, KP, mixed, s, nullptr, nullptr, nullptr, nullptr, nullptr)) return true;
+  return false;
+}
 
 // Stage sequences timed per candidate shape by the autotuner (after one
 // untimed sequence).
@@ -307,17 +324,17 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
   if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
   if (n_steps < 0) return fail(HEOM_E_INVALID, "n_steps must be >= 0");
   if (record_every < 1) return fail(HEOM_E_INVALID, "record_every must be >= 1");
-  // A forced tile launch shape must exist for every instance the tile kernel
-  // will run.
+  // A forced launch shape must exist for every instance the LDS-tiled
+  // kernels will run.
   const int forced = forced_shape(flags);
   if (forced >= kMaxTileShapes) return fail(HEOM_E_INVALID, "tile launch shape out of range");
   if (forced >= 0 && !(flags & (HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)))
     for (int k = 0; k < n; ++k) {
       const heom_hierarchy *h = hs[k];
       const bool mixed = precision == HEOM_FP32_MIXED;
-      const bool tiled = tile_shape_info(h->N, h->KP, mixed, 0, nullptr, nullptr, nullptr, nullptr);
-      if (h->h_real && tiled &&
-          !tile_shape_info(h->N, h->KP, mixed, forced, nullptr, nullptr, nullptr, nullptr))
+      if (h->h_real && has_tiled(h->N, h->KP, mixed) &&
+          !tile_shape_info(h->N, h->KP, mixed, forced, nullptr, nullptr, nullptr, nullptr,
+                           nullptr))
         return fail(HEOM_E_UNSUPPORTED, "tile launch shape " + std::to_string(forced) +
                                             " is not built for N=" + std::to_string(h->N) +
                                             ", K+1=" + std::to_string(h->KP));
@@ -394,7 +411,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real) {
       if (flags & HEOM_LANE_KERNEL) {
         if (has_fixed_kernel(h->N, h->KP)) kind = KernelKind::kLane;
-      } else if (has_tile_kernel(h->N, h->KP)) {
+      } else if (has_tiled(h->N, h->KP, mixed)) {
         kind = KernelKind::kTile;
       }
     }
@@ -403,26 +420,13 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   }
   std::vector<WorkItem> items;
   std::vector<Group> groups;
-  for (const auto &kv : by_key) {
-    Group g;
-    g.kind = static_cast<KernelKind>(std::get<0>(kv.first));
-    g.N = std::get<1>(kv.first);
-    g.KP = std::get<2>(kv.first);
-    g.shape = 0;
-    if (g.kind == KernelKind::kTile) {
-      g.ados_per_item = 64;
-      if (!tile_shape_info(g.N, g.KP, mixed, 0, &g.threads, nullptr, nullptr, nullptr))
-        return fail(HEOM_E_UNSUPPORTED, "no tile kernel for this hierarchy");
-    } else {
-      g.ados_per_item = block_ados();
-      g.threads = g.ados_per_item;
-    }
-    g.item_begin = static_cast<int64_t>(items.size());
+  // Appends the work list of `members` in items of `ados` ADOs, XCD-ordered.
+  auto add_list = [&](const std::vector<int> &members, int64_t ados, int64_t *begin,
+                      int64_t *count) {
     std::vector<WorkItem> mine;
-    for (int k : kv.second)
-      for (int64_t first = 0; first < hs[k]->n_ados; first += g.ados_per_item)
+    for (int k : members)
+      for (int64_t first = 0; first < hs[k]->n_ados; first += ados)
         mine.push_back({k, static_cast<int32_t>(first)});
-    g.n_tiles = static_cast<int64_t>(mine.size());
     if (xcd_remap()) {
       // Workgroup b runs on XCD b % kXcds.  Give XCD x the x-th contiguous
       // eighth of the list (consecutive tiles of the same instance), so that
@@ -436,8 +440,34 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
         perm[b] = mine[(b % kXcds) * len + b / kXcds];
       mine.swap(perm);
     }
+    *begin = static_cast<int64_t>(items.size());
+    *count = static_cast<int64_t>(mine.size());
     items.insert(items.end(), mine.begin(), mine.end());
-    g.n_items = static_cast<int64_t>(items.size()) - g.item_begin;
+  };
+  for (const auto &kv : by_key) {
+    Group g;
+    g.kind = static_cast<KernelKind>(std::get<0>(kv.first));
+    g.N = std::get<1>(kv.first);
+    g.KP = std::get<2>(kv.first);
+    g.shape = 0;
+    g.n_tiles = 0;
+    for (int k : kv.second) g.n_tiles += (hs[k]->n_ados + kPlanePad - 1) / kPlanePad;
+    if (g.kind == KernelKind::kTile) {
+      const bool tile = tile_shape_info(g.N, g.KP, mixed, 0, nullptr, nullptr, nullptr, nullptr,
+                                        nullptr);
+      const bool wide = tile_shape_info(g.N, g.KP, mixed, kWideShape, nullptr, nullptr, nullptr,
+                                        nullptr, nullptr);
+      if (tile) add_list(kv.second, kPlanePad, &g.begin[0], &g.count[0]);
+      if (wide) {
+        add_list(kv.second, 16, &g.begin[1], &g.count[1]);
+        HEOM_HIP(prepare_wide(g.N, g.N * g.KP, mixed), "wide kernel attributes");
+      }
+      g.shape = tile ? 0 : kWideShape;
+      tile_shape_info(g.N, g.KP, mixed, g.shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
+    } else {
+      g.threads = block_ados();
+      add_list(kv.second, g.threads, &g.begin[0], &g.count[0]);
+    }
     groups.push_back(g);
   }
   // Initialisation items (64 ADOs each) of the instances that start here.
@@ -528,20 +558,21 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   // buffers they leave behind before reading them, so the run is unchanged.
   for (Group &g : groups) {
     if (g.kind != KernelKind::kTile) continue;
-    int shape = forced_shape(flags);  // validated when the groups were formed
-    if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = 0;
+    int shape = forced_shape(flags);  // validated by check_common
+    if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = g.shape;
     if (shape < 0) {
       auto time_shape = [&](int s, double *us) -> int {
         int threads = 0;
-        tile_shape_info(g.N, g.KP, mixed, s, &threads, nullptr, nullptr, nullptr);
+        tile_shape_info(g.N, g.KP, mixed, s, nullptr, &threads, nullptr, nullptr, nullptr);
+        const int l = g.list(s);
         hipEvent_t ev[2] = {nullptr, nullptr};
         int rc = HEOM_OK;
         auto pseudo_step = [&]() {
           hipError_t e = hipSuccess;
           for (int st : {0, 1, 2, 1})
             if (e == hipSuccess)
-              e = launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.item_begin,
-                               static_cast<int>(g.n_items), threads, st, coef[st], -1, stream);
+              e = launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.begin[l],
+                               static_cast<int>(g.count[l]), threads, st, coef[st], -1, stream);
           return e;
         };
         hipError_t e = hipEventCreate(&ev[0]);
@@ -563,14 +594,15 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       if (rc) return rc;
     }
     g.shape = shape;
-    tile_shape_info(g.N, g.KP, mixed, shape, &g.threads, nullptr, nullptr, nullptr);
+    tile_shape_info(g.N, g.KP, mixed, shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
   }
   // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.
   auto enqueue_step = [&](hipStream_t s) -> hipError_t {
     for (int st = 0; st < 4; ++st)
       for (const Group &g : groups) {
+        const int l = g.list(g.shape);
         hipError_t e = launch_stage(g.kind, mixed, g.N, g.KP, g.shape, d_descs,
-                                    d_work + g.item_begin, static_cast<int>(g.n_items), g.threads,
+                                    d_work + g.begin[l], static_cast<int>(g.count[l]), g.threads,
                                     st, coef[st], -1, s);
         if (e != hipSuccess) return e;
       }
@@ -668,7 +700,7 @@ SlotScratch slot_scratch(heom_hierarchy *const *hs, int n) {
   SlotScratch s;
   s.descs = 0;
   size_t off = align_up(sizeof(InstDesc) * n);
-  for (int k = 0; k < n; ++k) s.work_cap += 2 * ((hs[k]->n_ados + kPlanePad - 1) / kPlanePad) + 8;
+  for (int k = 0; k < n; ++k) s.work_cap += work_items_cap(hs[k]->n_ados);
   s.work = off;
   s.total = align_up(off + sizeof(WorkItem) * s.work_cap);
   return s;
@@ -988,15 +1020,16 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
 int heom_tile_shape_count(void) { return kMaxTileShapes; }
 
 int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision, int32_t shape,
-                         int32_t *threads, int32_t *elems_per_wave, int32_t *chunk,
-                         int32_t *min_waves_per_simd) {
+                         int32_t *ados_per_workgroup, int32_t *threads, int32_t *elems_per_wave,
+                         int32_t *chunk, int32_t *min_waves_per_simd) {
   if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
     return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
   if (shape < 0 || shape >= kMaxTileShapes) return fail(HEOM_E_INVALID, "shape out of range");
-  int t = 0, e = 0, c = 0, w = 0;
-  if (!tile_shape_info(n_sites, modes_per_site, precision == HEOM_FP32_MIXED, shape, &t, &e, &c,
-                       &w))
-    return fail(HEOM_E_UNSUPPORTED, "the tile kernel is not built for this N, K+1 and shape");
+  int a = 0, t = 0, e = 0, c = 0, w = 0;
+  if (!tile_shape_info(n_sites, modes_per_site, precision == HEOM_FP32_MIXED, shape, &a, &t, &e,
+                       &c, &w))
+    return fail(HEOM_E_UNSUPPORTED, "no kernel is built for this N, K+1 and launch shape");
+  if (ados_per_workgroup) *ados_per_workgroup = a;
   if (threads) *threads = t;
   if (elems_per_wave) *elems_per_wave = e;
   if (chunk) *chunk = c;

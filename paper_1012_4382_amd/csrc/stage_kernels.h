@@ -565,7 +565,7 @@ __host__ __device__ constexpr int ent_sg(int r, int c) { return r > c ? -1 : 1; 
 struct TileShape {
   int elems_per_wave, chunk, min_waves;
 };
-constexpr int kTileShapes = kMaxTileShapes;
+constexpr int kTileShapes = kWideShape;
 constexpr TileShape kShapesF64[kTileShapes] = {{7, 2, 1}, {7, 7, 1}, {2, 2, 1}, {4, 2, 1}, {2, 1, 7}};
 constexpr TileShape kShapesF32[kTileShapes] = {{4, 4, 1}, {4, 2, 1}, {2, 2, 1}, {7, 2, 1}, {2, 1, 7}};
 __host__ __device__ constexpr TileShape tile_shape(bool fp64, int s) {
@@ -610,7 +610,8 @@ struct TileCtx {
   const HEOM_GLOBAL T *X;             // stage input planes (neighbour gathers)
   const HEOM_GLOBAL T *Yp;            // state planes
   HEOM_GLOBAL T *Out;                 // output planes
-  const HEOM_GLOBAL double *x0, *y0;  // FP64 sigma_0 (mixed precision)
+  const double *sx0;                  // LDS copy of the FP64 sigma_0 stage input (mixed)
+  const HEOM_GLOBAL double *y0;       // FP64 sigma_0 state (mixed precision)
   HEOM_GLOBAL double *out0;
   int64_t S, i;
   int lane;
@@ -686,7 +687,7 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
   const int lane = c.lane;
   auto xe = [&](int e) -> C {
     if constexpr (X0SRC)
-      return e < N * N ? static_cast<C>(c.x0[e]) : C(0);
+      return e < N * N ? static_cast<C>(c.sx0[e]) : C(0);
     else
       return static_cast<C>(c.sx[e * kTile + lane]);
   };
@@ -804,6 +805,7 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   constexpr int CH0 = tile_shape(sizeof(T) == 8, SHAPE).chunk;
   constexpr bool MIXED = sizeof(T) == 4;
   __shared__ T sx[(N2 + 1) * kTile];
+  __shared__ double sx0[MIXED ? N2 : 1];  // FP64 sigma_0 stage input, tile of ADO 0 only
   __shared__ int32_t sup[M * kTile];
   __shared__ int32_t sdn[M * kTile];
   __shared__ uint8_t socc[M * kTile];
@@ -847,6 +849,10 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
     if (e < N2) sx[e * kTile + lane] = valid ? vx[r] : T(0);
   }
   if (wave == 0) sx[N2 * kTile + lane] = T(0);
+  if constexpr (MIXED) {
+    if (w.first == 0)
+      for (int e = threadIdx.x; e < N2; e += blockDim.x) sx0[e] = bufs.x0[e];
+  }
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
     const int m = wave + r * W;
@@ -871,7 +877,7 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                  X,
                  gmem(static_cast<const T *>(bufs.y)),
                  gmem(static_cast<T *>(bufs.out)),
-                 gmem(bufs.x0),
+                 sx0,
                  gmem(bufs.y0),
                  gmem(bufs.out0),
                  S,
@@ -889,10 +895,283 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   if (is0 && wave == 0) {
     scalar_update(d, bufs, N, coef, [&](int s) {
       if constexpr (MIXED)
-        return bufs.x0[s];
+        return sx0[s];
       else
         return static_cast<double>(sx[s * kTile + lane]);
     });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wide kernel: runtime N up to kWideMaxN, real H.
+//
+// A 64-ADO tile of a large system does not fit in LDS (N = 24 in FP64 would
+// need 295 KB), so this kernel stages kWideAdos = 16 consecutive ADOs, with
+// the Hamiltonian and the neighbour tables, and spreads a wave over 4 packed
+// elements x 16 ADOs: lane l handles ADO l % 16 of the tile and element slot
+// l / 16.  Each element plane is then read in 16-ADO (128-byte in FP64)
+// segments.  The commutator visits only the k where H_ak or H_kb is nonzero
+// (row masks built in LDS), in increasing k: for the chains and rings of the
+// serving workload that is at most 6 of the N terms, which keeps the LDS
+// traffic of the product small.  Each element is computed with the same
+// sequence of operations as in the tile kernel (terms with H = 0 are exact
+// no-ops there), so the two kernels agree bitwise where both exist.
+// ---------------------------------------------------------------------------
+
+constexpr int kWideAdos = 16;
+constexpr int kWideWaves = 16;
+constexpr int kWideSlots = kWideWaves * (64 / kWideAdos);  // element slots per workgroup
+constexpr int kWideMaxN = 32;
+
+// LDS layout of the wide kernel (byte offsets; every region 16-byte aligned).
+struct WideLds {
+  int x, h, nz, dec, dl, cr, ci, nu, up, dn, occ, pa, pb, x0, total;
+};
+__host__ __device__ inline int wide_align(int v) { return (v + 15) & ~15; }
+__host__ __device__ inline WideLds wide_lds(int N, int M, int s) {
+  const int P = N * (N + 1) / 2;
+  WideLds L;
+  L.x = 0;                                                    // T [N*N + 1][kWideAdos]
+  L.h = wide_align(L.x + (N * N + 1) * kWideAdos * s);        // double [N*N]
+  L.nz = wide_align(L.h + N * N * 8);                         // uint32 [N] row masks
+  L.dec = wide_align(L.nz + N * 4);                           // double [N] (trap + rec) / 2
+  L.dl = wide_align(L.dec + N * 8);                           // double [N] delta
+  L.cr = wide_align(L.dl + N * 8);                            // double [M]
+  L.ci = wide_align(L.cr + M * 8);                            // double [M]
+  L.nu = wide_align(L.ci + M * 8);                            // double [M]
+  L.up = wide_align(L.nu + M * 8);                            // int32 [M][kWideAdos]
+  L.dn = wide_align(L.up + M * kWideAdos * 4);                // int32 [M][kWideAdos]
+  L.occ = wide_align(L.dn + M * kWideAdos * 4);               // uint8 [M][kWideAdos]
+  L.pa = wide_align(L.occ + M * kWideAdos);                   // uint8 [P] element -> a
+  L.pb = wide_align(L.pa + P);                                // uint8 [P] element -> b
+  L.x0 = wide_align(L.pb + P);                                // double [N*N] (FP32 storage)
+  L.total = wide_align(L.x0 + (s == 4 ? N * N * 8 : 0));
+  return L;
+}
+
+template <typename T>
+struct WideCtx {
+  int N, KP, t;
+  const T *sx;
+  const double *sh, *sdec, *sdl, *scr, *sci;
+  const uint32_t *snz;
+  const int32_t *sup, *sdn;
+  const uint8_t *socc;
+  const HEOM_GLOBAL T *X, *Yp;
+  HEOM_GLOBAL T *Out;
+  const double *sx0;  // LDS copy of the FP64 sigma_0 stage input (FP32 storage)
+  const HEOM_GLOBAL double *y0;
+  HEOM_GLOBAL double *out0;
+  int64_t S, i;
+  double damp, coef;
+};
+
+// Element (a, b) of the lane's ADO: the operations of tile_load and
+// tile_finish with runtime a, b.  X0SRC reads sigma_0 from its FP64 copies.
+template <typename C, typename T, bool X0SRC>
+__device__ __forceinline__ void wide_element(const WideCtx<T> &c, int a, int b) {
+#pragma clang fp contract(off)
+  const int N = c.N, KP = c.KP, t = c.t;
+  const int E = ent_re(N, a, b);
+  const HEOM_GLOBAL T *pre = c.X + E * c.S;
+  const HEOM_GLOBAL T *pim = c.X + (E + 1) * c.S;
+  const uint32_t self = static_cast<uint32_t>(c.i);
+  auto xe = [&](int e) -> C {
+    if constexpr (X0SRC)
+      return e < N * N ? static_cast<C>(c.sx0[e]) : C(0);
+    else
+      return static_cast<C>(c.sx[e * kWideAdos + t]);
+  };
+  auto off = [&](int j) -> uint32_t {
+    return (j >= 0 ? static_cast<uint32_t>(j) : self) * static_cast<uint32_t>(sizeof(T));
+  };
+  C sr = C(0), si = C(0);
+  uint32_t mask = c.snz[a] | c.snz[b];
+  while (mask) {
+    const int k = __builtin_ctz(mask);
+    mask &= mask - 1;
+    const C hak = static_cast<C>(c.sh[a * N + k]);
+    const C hkb = static_cast<C>(c.sh[k * N + b]);
+    const C xkb_r = xe(ent_re(N, k, b));
+    const C xkb_i = static_cast<C>(ent_sg(k, b)) * xe(ent_im(N, k, b));
+    const C xak_r = xe(ent_re(N, a, k));
+    const C xak_i = static_cast<C>(ent_sg(a, k)) * xe(ent_im(N, a, k));
+    sr = fmad(-xak_r, hkb, fmad(hak, xkb_r, sr));
+    si = fmad(-xak_i, hkb, fmad(hak, xkb_i, si));
+  }
+  C ar = si, ai = -sr;
+  const C xr = xe(E), xi = xe(ent_im(N, a, b));
+  C dec = static_cast<C>(c.damp) + static_cast<C>(c.sdec[a]) + static_cast<C>(c.sdec[b]);
+  if (a != b) dec += static_cast<C>(c.sdl[a]) + static_cast<C>(c.sdl[b]);
+  ar = fmad(-dec, xr, ar);
+  ai = fmad(-dec, xi, ai);
+  for (int k = 0; k < KP; ++k) {
+    const int ma = a * KP + k;
+    const int mb = b * KP + k;
+    if (a != b) {
+      const int ja = c.sup[ma * kWideAdos + t];
+      const int jb = c.sup[mb * kWideAdos + t];
+      const C yar = static_cast<C>(ld_off(pre, off(ja))), yai = static_cast<C>(ld_off(pim, off(ja)));
+      const C ybr = static_cast<C>(ld_off(pre, off(jb))), ybi = static_cast<C>(ld_off(pim, off(jb)));
+      const C fa = ja >= 0 ? C(1) : C(0);
+      const C fb = jb >= 0 ? C(1) : C(0);
+      ar = fmad(-fa, yai, fmad(fb, ybi, ar));
+      ai = fmad(-fb, ybr, fmad(fa, yar, ai));
+    }
+    const int ja = c.sdn[ma * kWideAdos + t];
+    const int jb = c.sdn[mb * kWideAdos + t];
+    const C zar = static_cast<C>(ld_off(pre, off(ja)));
+    const C zbr = static_cast<C>(ld_off(pre, off(jb)));
+    const C zai = (a == b) ? C(0) : static_cast<C>(ld_off(pim, off(ja)));
+    const C zbi = (a == b) ? C(0) : static_cast<C>(ld_off(pim, off(jb)));
+    const C na = static_cast<C>(c.socc[ma * kWideAdos + t]);
+    const C nb = static_cast<C>(c.socc[mb * kWideAdos + t]);
+    const C car = na * static_cast<C>(c.scr[ma]), cai = na * static_cast<C>(c.sci[ma]);
+    const C cbr = nb * static_cast<C>(c.scr[mb]), cbi = nb * static_cast<C>(c.sci[mb]);
+    ar = fmad(-car, zai, fmad(-cai, zar, ar));
+    ai = fmad(-cai, zai, fmad(car, zar, ai));
+    ar = fmad(-cbi, zbr, fmad(cbr, zbi, ar));
+    ai = fmad(-cbi, zbi, fmad(-cbr, zbr, ai));
+  }
+  C str, sti = C(0);
+  const uint32_t oi = self * static_cast<uint32_t>(sizeof(T));
+  if constexpr (X0SRC) {
+    str = static_cast<C>(c.y0[E]);
+    if (a != b) sti = static_cast<C>(c.y0[E + 1]);
+  } else {
+    str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
+    if (a != b) sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
+  }
+  const C coef = static_cast<C>(c.coef);
+  const C nr = fmad(coef, ar, str);
+  const C ni = fmad(coef, ai, sti);
+  if constexpr (X0SRC) {
+    c.out0[E] = nr;
+    if (a != b) c.out0[E + 1] = ni;
+  }
+  st_off(c.Out + E * c.S, oi, static_cast<T>(nr));
+  if (a != b) st_off(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kWideWaves)
+    stage_wide(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
+               double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
+  extern __shared__ __align__(16) char wide_smem[];
+  constexpr bool MIXED = sizeof(T) == 4;
+  const WorkItem w = work[blockIdx.x];
+  const InstDesc &d = descs[w.inst];
+  const int N = d.N, M = d.M, KP = d.KP, N2 = N * N, P = N * (N + 1) / 2;
+  const WideLds L = wide_lds(N, M, static_cast<int>(sizeof(T)));
+  T *sx = reinterpret_cast<T *>(wide_smem + L.x);
+  double *sh = reinterpret_cast<double *>(wide_smem + L.h);
+  uint32_t *snz = reinterpret_cast<uint32_t *>(wide_smem + L.nz);
+  double *sdec = reinterpret_cast<double *>(wide_smem + L.dec);
+  double *sdl = reinterpret_cast<double *>(wide_smem + L.dl);
+  double *scr = reinterpret_cast<double *>(wide_smem + L.cr);
+  double *sci = reinterpret_cast<double *>(wide_smem + L.ci);
+  double *snu = reinterpret_cast<double *>(wide_smem + L.nu);
+  int32_t *sup = reinterpret_cast<int32_t *>(wide_smem + L.up);
+  int32_t *sdn = reinterpret_cast<int32_t *>(wide_smem + L.dn);
+  uint8_t *socc = reinterpret_cast<uint8_t *>(wide_smem + L.occ);
+  uint8_t *spa = reinterpret_cast<uint8_t *>(wide_smem + L.pa);
+  uint8_t *spb = reinterpret_cast<uint8_t *>(wide_smem + L.pb);
+  double *sx0 = reinterpret_cast<double *>(wide_smem + L.x0);
+
+  const StageBufs bufs = stage_bufs(d, stage);
+  const int64_t S = d.stride;
+  const int tid = threadIdx.x;
+  const HEOM_GLOBAL T *X = gmem(static_cast<const T *>(bufs.x));
+  const HEOM_GLOBAL double *Pg = gmem(d.params);
+  const ParamOffsets o = param_offsets(N, M);
+  // Stage the tile (invalid ADOs of the last tile read ADO 0 and store 0),
+  // the parameters, the neighbour tables and the element map.
+  for (int idx = tid; idx < N2 * kWideAdos; idx += blockDim.x) {
+    const int e = idx / kWideAdos, t = idx % kWideAdos;
+    const int64_t i = static_cast<int64_t>(w.first) + t;
+    const T v = X[e * S + (i < d.n_ados ? i : 0)];
+    sx[idx] = i < d.n_ados ? v : T(0);
+  }
+  if (tid < kWideAdos) sx[N2 * kWideAdos + tid] = T(0);
+  for (int idx = tid; idx < N2; idx += blockDim.x) sh[idx] = Pg[o.h_re + idx];
+  for (int idx = tid; idx < N; idx += blockDim.x) {
+    uint32_t m = 0;
+    for (int k = 0; k < N; ++k)
+      if (Pg[o.h_re + idx * N + k] != 0.0) m |= 1u << k;
+    snz[idx] = m;
+    sdec[idx] = Pg[o.half_gamma + idx];
+    sdl[idx] = Pg[o.delta + idx];
+  }
+  for (int idx = tid; idx < M; idx += blockDim.x) {
+    scr[idx] = Pg[o.c_re + idx];
+    sci[idx] = Pg[o.c_im + idx];
+    snu[idx] = Pg[o.nu + idx];
+  }
+  for (int idx = tid; idx < M * kWideAdos; idx += blockDim.x) {
+    const int m = idx / kWideAdos, t = idx % kWideAdos;
+    const int64_t i = static_cast<int64_t>(w.first) + t;
+    const bool ok = i < d.n_ados;
+    sup[idx] = ok ? gmem(d.up)[m * S + i] : -1;
+    sdn[idx] = ok ? gmem(d.down)[m * S + i] : -1;
+    socc[idx] = ok ? gmem(d.occ)[m * S + i] : 0;
+  }
+  for (int p = tid; p < P; p += blockDim.x) {
+    spa[p] = static_cast<uint8_t>(elem_a(N, p));
+    spb[p] = static_cast<uint8_t>(elem_b(N, p));
+  }
+  if constexpr (MIXED) {
+    if (w.first == 0)
+      for (int e = tid; e < N2; e += blockDim.x) sx0[e] = bufs.x0[e];
+  }
+  __syncthreads();
+
+  const int lane = tid & 63;
+  const int t = lane % kWideAdos;
+  const int slot = (tid >> 6) * (64 / kWideAdos) + lane / kWideAdos;
+  const int64_t i = static_cast<int64_t>(w.first) + t;
+  auto make_ctx = [&](int tt, int64_t ii) {
+    double damp = 0.0;
+    for (int m = 0; m < M; ++m)
+      damp = fmad(static_cast<double>(socc[m * kWideAdos + tt]), snu[m], damp);
+    return WideCtx<T>{N,
+                      KP,
+                      tt,
+                      sx,
+                      sh,
+                      sdec,
+                      sdl,
+                      scr,
+                      sci,
+                      snz,
+                      sup,
+                      sdn,
+                      socc,
+                      X,
+                      gmem(static_cast<const T *>(bufs.y)),
+                      gmem(static_cast<T *>(bufs.out)),
+                      sx0,
+                      gmem(bufs.y0),
+                      gmem(bufs.out0),
+                      S,
+                      ii,
+                      damp,
+                      coef};
+  };
+  // With FP32 storage, sigma_0 is computed separately below, in FP64.
+  if (i < d.n_ados && !(MIXED && i == 0)) {
+    const WideCtx<T> ctx = make_ctx(t, i);
+    for (int p = slot; p < P; p += kWideSlots) wide_element<T, T, false>(ctx, spa[p], spb[p]);
+    if (!MIXED && i == 0 && slot == 0)
+      scalar_update(d, bufs, N, coef, [&](int e) { return static_cast<double>(sx[e * kWideAdos]); });
+  }
+  if constexpr (MIXED) {
+    // sigma_0 in FP64 from its FP64 copies, its elements spread over the
+    // whole workgroup of the first tile.
+    if (w.first == 0) {
+      const WideCtx<T> ctx0 = make_ctx(0, 0);
+      for (int p = tid; p < P; p += blockDim.x) wide_element<double, T, true>(ctx0, spa[p], spb[p]);
+      if (tid == 0) scalar_update(d, bufs, N, coef, [&](int e) { return sx0[e]; });
+    }
   }
 }
 

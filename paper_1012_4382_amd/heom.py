@@ -104,7 +104,7 @@ _SIGNATURES = [
                                           _P(_P(_d)), _P(_P(_d))]),
     ("heom_tile_shape_count", ctypes.c_int, []),
     ("heom_tile_shape_info", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i32, _P(_i32), _P(_i32),
-                                            _P(_i32), _P(_i32)]),
+                                            _P(_i32), _P(_i32), _P(_i32)]),
     ("heom_autotune_lookup", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i64, _P(_i32), _P(_d)]),
     ("heom_autotune_clear", None, []),
     ("heom_destroy", None, [_vp]),
@@ -376,17 +376,17 @@ def tile_shape_count() -> int:
 
 
 def tile_shape_info(n_sites: int, modes_per_site: int, precision="fp64", shape: int = 0):
-    """(threads per workgroup, target elements per wave, load chunk, minimum
-    waves per SIMD) of a tile launch shape, or None if that shape is not built
-    for n_sites."""
-    t, e, c, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(ADOs per workgroup, threads per workgroup, elements per wave, load
+    chunk, minimum waves per SIMD) of a launch shape, or None if that shape is
+    not built for n_sites."""
+    a, t, e, c, w = (ctypes.c_int32() for _ in range(5))
     st = library().heom_tile_shape_info(int(n_sites), int(modes_per_site), PRECISIONS[precision],
-                                        int(shape), ctypes.byref(t), ctypes.byref(e),
-                                        ctypes.byref(c), ctypes.byref(w))
+                                        int(shape), ctypes.byref(a), ctypes.byref(t),
+                                        ctypes.byref(e), ctypes.byref(c), ctypes.byref(w))
     if st == HEOM_E_UNSUPPORTED:
         return None
     _check(st, "heom_tile_shape_info")
-    return t.value, e.value, c.value, w.value
+    return a.value, t.value, e.value, c.value, w.value
 
 
 def autotune_lookup(n_sites: int, modes_per_site: int, n_tiles: int, precision="fp64"):

@@ -126,14 +126,17 @@ class Engine:
 
     def __init__(self, backend, hbm_budget_bytes: int, chunk_steps: int = 200,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep, max_active: Optional[int] = None):
         if hbm_budget_bytes <= 0:
             raise ValueError("hbm_budget_bytes must be positive")
         if chunk_steps < 1:
             raise ValueError("chunk_steps must be >= 1")
+        if max_active is not None and max_active < 1:
+            raise ValueError("max_active must be >= 1")
         self.backend = backend
         self.budget = int(hbm_budget_bytes)
         self.chunk_steps = int(chunk_steps)
+        self.max_active = max_active  # None: as many as the budget admits
         self.clock = clock
         self.sleep = sleep
         self.waiting: deque = deque()
@@ -192,7 +195,8 @@ class Engine:
     def _admit(self) -> None:
         # First come, first served: the head of the queue waits for memory; a
         # smaller request behind it does not overtake it.
-        while self.waiting and self.in_use + self.waiting[0][1] <= self.budget:
+        while (self.waiting and self.in_use + self.waiting[0][1] <= self.budget and
+               (self.max_active is None or len(self.active) < self.max_active)):
             req, nbytes, prepared = self.waiting.popleft()
             try:
                 slot = self.backend.admit(req, prepared)
@@ -251,16 +255,22 @@ class Engine:
         self.active = still
         return True
 
-    def run(self, requests) -> dict:
+    def run(self, requests, on_finish: Optional[Callable[[Request], None]] = None) -> dict:
         """Serves `requests` (sorted by arrival_s, seconds from the start) and
-        returns the metrics."""
+        returns the metrics.  ``on_finish`` is called with each request that
+        leaves the engine (done, failed or rejected), in order."""
         pending = deque(sorted(requests, key=lambda r: r.arrival_s))
         self._now()
+        reported = len(self.finished)
         while pending or self.waiting or self.active:
             now = self._now()
             while pending and pending[0].arrival_s <= now:
                 self.submit(pending.popleft())
             ran = self.step()
+            if on_finish is not None:
+                for r in self.finished[reported:]:
+                    on_finish(r)
+                reported = len(self.finished)
             if not ran and pending:
                 self.sleep(max(0.0, pending[0].arrival_s - self._now()))
         return self.metrics()

@@ -173,27 +173,34 @@ def test_product_path_does_not_use_the_oracle():
 
 
 def test_tile_shapes_and_forced_shape_validation():
-    """Launch shapes of the tile kernel: every N <= 12 has shape 0, N <= 8 all
-    shapes; a workgroup's waves divide the N(N+1)/2 packed elements; a forced
-    shape that is out of range or not built is rejected before device work."""
+    """Launch shapes: the 64-ADO tile kernel in shapes 0-4 (every N <= 12 has
+    shape 0, N <= 8 all five), its waves dividing the N(N+1)/2 packed
+    elements; the 16-ADO wide kernel as shape 5 for N <= 32; a forced shape
+    that is out of range or not built is rejected before device work."""
     lib = heom.library()
     count = heom.tile_shape_count()
-    assert count == 5
-    for N in range(1, 13):
+    wide = count - 1
+    assert count == 6
+    for N in range(1, 34):
         P = N * (N + 1) // 2
         for prec in ("fp64", "fp32"):
-            for s in range(count):
+            for s in range(wide):
                 info = heom.tile_shape_info(N, 1, prec, s)
-                if s == 0 or N <= 8:
-                    assert info is not None, (N, prec, s)
+                assert (info is not None) == (N <= 8 or (s == 0 and N <= 12)), (N, prec, s)
                 if info is not None:
-                    threads, epw, chunk, waves = info
-                    assert threads % 64 == 0 and 64 <= threads <= 1024
+                    ados, threads, epw, chunk, waves = info
+                    assert ados == 64 and threads % 64 == 0 and 64 <= threads <= 1024
                     assert P % (threads // 64) == 0 and epw >= 1 and chunk >= 1
                     assert 1 <= waves <= 8
-    assert heom.tile_shape_info(13, 1, "fp64", 0) is None
-    assert lib.heom_tile_shape_info(7, 1, 0, count, None, None, None, None) == heom.HEOM_E_INVALID
-    assert lib.heom_tile_shape_info(7, 1, 5, 0, None, None, None, None) == heom.HEOM_E_UNSUPPORTED
+            for kp in (1, 2, 4):
+                info = heom.tile_shape_info(N, kp, prec, wide)
+                assert (info is not None) == (N <= 32), (N, kp, prec)
+                if info is not None:
+                    assert info[:2] == (16, 1024)
+    assert lib.heom_tile_shape_info(7, 1, 0, count, None, None, None, None, None) == \
+        heom.HEOM_E_INVALID
+    assert lib.heom_tile_shape_info(7, 1, 5, 0, None, None, None, None, None) == \
+        heom.HEOM_E_UNSUPPORTED
 
     H = np.diag(np.linspace(12300.0, 12500.0, 12)) + np.diag(np.full(11, -80.0), 1) \
         + np.diag(np.full(11, -80.0), -1)

@@ -152,3 +152,21 @@ def test_engine_argument_validation():
         Engine(OracleBackend(VClock()), hbm_budget_bytes=0)
     with pytest.raises(ValueError):
         Engine(OracleBackend(VClock()), hbm_budget_bytes=10, chunk_steps=0)
+    with pytest.raises(ValueError):
+        Engine(OracleBackend(VClock()), hbm_budget_bytes=10, max_active=0)
+
+
+def test_one_at_a_time_baseline_and_finish_callback():
+    """max_active=1 serves strictly one request at a time (the FIFO baseline);
+    on_finish sees every request once, in completion order."""
+    clock = VClock()
+    be = OracleBackend(clock)
+    eng = Engine(be, hbm_budget_bytes=10**9, chunk_steps=30, clock=clock, sleep=clock.sleep,
+                 max_active=1)
+    reqs = [_req(i, arrival=0.0, steps=60) for i in range(3)]
+    seen = []
+    m = eng.run(reqs, on_finish=lambda r: seen.append(r.id))
+    assert m["completed"] == 3 and seen == [0, 1, 2]
+    assert all(len(c) == 1 for c in be.calls)
+    assert [r.admit_s for r in reqs] == sorted(r.admit_s for r in reqs)
+    assert reqs[1].admit_s >= reqs[0].finish_s
