@@ -221,8 +221,9 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
  * wave64 and LDS).  Shapes 0-4 are the 64-ADO tile kernel (N <= 12), which
  * differ in the waves per workgroup, the packed elements each wave computes,
  * how many elements have their neighbour gathers in flight together and the
- * register budget.  Shape 5 is the 16-ADO wide kernel (N <= 32 while its LDS
- * fits: all N <= 32 for K + 1 <= 4).  Every shape computes each element with
+ * register budget.  Shape 5 is the 16-ADO wide kernel (N <= 32 and K + 1 <= 4
+ * while its LDS fits 160 KB: all of them except FP64 with N = 32 and
+ * K + 1 >= 3; state buffers below 4 GiB).  Every shape computes each element with
  * the same operations, so results do not depend on the shape.  Unless a call
  * passes HEOM_NO_AUTOTUNE (then shape 0, or 5 where 0 is not built) or
  * HEOM_TILE_SHAPE(s), the first call that meets a new key (GPU architecture,

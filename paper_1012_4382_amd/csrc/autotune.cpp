@@ -131,13 +131,14 @@ void append_file_locked(const Key &k, const Entry &e) {
 }  // namespace
 
 int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
+                    const std::function<bool(int)> &available,
                     const std::function<int(int, double *)> &time_shape, int *shape_out) {
   const Key key(arch_of(device), mixed ? 1 : 0, N, KP, log2_floor(n_tiles));
   {
     std::lock_guard<std::mutex> lock(g_mu);
     read_file_locked();
     auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
+    if (it != g_cache.end() && available(it->second.shape)) {
       *shape_out = it->second.shape;
       return HEOM_OK;
     }
@@ -150,7 +151,8 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
   int cand[kMaxTileShapes], n_cand = 0;
   for (int s = 0; s < kMaxTileShapes; ++s) {
     int ados = 0, threads = 0, epw = 0, chunk = 0, waves = 0;
-    if (!tile_shape_info(N, KP, mixed, s, &ados, &threads, &epw, &chunk, &waves)) continue;
+    if (!available(s) || !tile_shape_info(N, KP, mixed, s, &ados, &threads, &epw, &chunk, &waves))
+      continue;
     bool dup = false;
     for (int q = 0; q < n_seen; ++q)
       dup = dup || (seen[q][0] == ados && seen[q][1] == threads && seen[q][2] == chunk &&
@@ -184,7 +186,7 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
   std::lock_guard<std::mutex> lock(g_mu);
   auto ins = g_cache.emplace(key, e);
   if (ins.second) append_file_locked(key, e);
-  *shape_out = ins.first->second.shape;
+  *shape_out = available(ins.first->second.shape) ? ins.first->second.shape : e.shape;
   return HEOM_OK;
 }
 

@@ -145,9 +145,10 @@ int build_tables(heom_hierarchy *h);
 bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threads,
                      int *elems_per_wave, int *chunk, int *min_waves);
 // autotune.cpp: the launch shape of a tile group of n_tiles tiles, from the
-// cache or, for a new key, by timing each candidate with time_shape(shape,
-// &microseconds_per_launch).
+// cache or, for a new key, by timing each candidate that available(shape)
+// admits with time_shape(shape, &microseconds_per_launch).
 int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
+                    const std::function<bool(int)> &available,
                     const std::function<int(int, double *)> &time_shape, int *shape_out);
 int autotune_lookup(int device, bool mixed, int N, int KP, int64_t n_tiles, int *shape,
                     double *us);

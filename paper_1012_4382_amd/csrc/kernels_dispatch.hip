@@ -62,8 +62,23 @@ bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false, 0) != nul
 // gfx950 CU.
 bool has_wide_kernel(int N, int M, bool mixed) {
   constexpr int kLdsBytes = 160 * 1024;
-  return N >= 1 && N <= kWideMaxN && wide_lds(N, M, mixed ? 4 : 8).total <= kLdsBytes;
+  return N >= 1 && N <= kWideMaxN && M % N == 0 && M / N <= kWideMaxKP &&
+         wide_lds(N, M, mixed ? 4 : 8).total <= kLdsBytes;
 }
+
+namespace {
+template <typename T>
+const void *wide_kernel(int KP) {
+  static_assert(kWideMaxKP == 4, "one instance per K+1");
+  switch (KP) {
+    case 1: return reinterpret_cast<const void *>(&stage_wide<T, 1>);
+    case 2: return reinterpret_cast<const void *>(&stage_wide<T, 2>);
+    case 3: return reinterpret_cast<const void *>(&stage_wide<T, 3>);
+    case 4: return reinterpret_cast<const void *>(&stage_wide<T, 4>);
+  }
+  return nullptr;
+}
+}  // namespace
 
 bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threads,
                      int *elems_per_wave, int *chunk, int *min_waves) {
@@ -97,8 +112,8 @@ bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threa
 // once per configuration before any launch (and before graph capture).
 hipError_t prepare_wide(int N, int M, bool mixed) {
   const int bytes = wide_lds(N, M, mixed ? 4 : 8).total;
-  const void *k = mixed ? reinterpret_cast<const void *>(&stage_wide<float>)
-                        : reinterpret_cast<const void *>(&stage_wide<double>);
+  const void *k = mixed ? wide_kernel<float>(M / N) : wide_kernel<double>(M / N);
+  if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -107,12 +122,11 @@ hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         int stage, double coef, int hist_slot, hipStream_t stream) {
   if (kind == KernelKind::kTile && shape == kWideShape) {
     const size_t lds = static_cast<size_t>(wide_lds(N, N * KP, mixed ? 4 : 8).total);
-    if (mixed)
-      hipLaunchKernelGGL(stage_wide<float>, dim3(n_items), dim3(block), lds, stream, descs, work,
-                         stage, coef, hist_slot);
-    else
-      hipLaunchKernelGGL(stage_wide<double>, dim3(n_items), dim3(block), lds, stream, descs, work,
-                         stage, coef, hist_slot);
+    const StageKernel k = reinterpret_cast<StageKernel>(
+        const_cast<void *>(mixed ? wide_kernel<float>(KP) : wide_kernel<double>(KP)));
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(n_items), dim3(block), lds, stream, descs, work, stage, coef,
+                       hist_slot);
     return hipGetLastError();
   }
   StageKernel k = nullptr;

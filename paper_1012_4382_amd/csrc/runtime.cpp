@@ -282,10 +282,21 @@ struct Group {
   int list(int s) const { return (kind == KernelKind::kTile && s == kWideShape) ? 1 : 0; }
 };
 
-// Whether (N, K+1, storage) has any LDS-tiled launch shape.
-bool has_tiled(int N, int KP, bool mixed) {
+// Whether launch shape s can run hierarchy h: built for its N and K+1, and
+// for the wide kernel, whose loads use 32-bit byte offsets from the buffer
+// bases, state buffers below 4 GiB.
+bool shape_ok(const heom_hierarchy *h, bool mixed, int s) {
+  if (!tile_shape_info(h->N, h->KP, mixed, s, nullptr, nullptr, nullptr, nullptr, nullptr))
+    return false;
+  if (s != kWideShape) return true;
+  const uint64_t bytes = static_cast<uint64_t>(h->N) * h->N * h->stride * (mixed ? 4 : 8);
+  return bytes < (uint64_t{1} << 32);
+}
+
+// Whether h has any LDS-tiled launch shape.
+bool has_tiled(const heom_hierarchy *h, bool mixed) {
   for (int s = 0; s < kMaxTileShapes; ++s)
-    if (tile_shape_info(N, KP, mixed, s, nullptr, nullptr, nullptr, nullptr, nullptr)) return true;
+    if (shape_ok(h, mixed, s)) return true;
   return false;
 }
 
@@ -332,9 +343,7 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
     for (int k = 0; k < n; ++k) {
       const heom_hierarchy *h = hs[k];
       const bool mixed = precision == HEOM_FP32_MIXED;
-      if (h->h_real && has_tiled(h->N, h->KP, mixed) &&
-          !tile_shape_info(h->N, h->KP, mixed, forced, nullptr, nullptr, nullptr, nullptr,
-                           nullptr))
+      if (h->h_real && has_tiled(h, mixed) && !shape_ok(h, mixed, forced))
         return fail(HEOM_E_UNSUPPORTED, "tile launch shape " + std::to_string(forced) +
                                             " is not built for N=" + std::to_string(h->N) +
                                             ", K+1=" + std::to_string(h->KP));
@@ -411,7 +420,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real) {
       if (flags & HEOM_LANE_KERNEL) {
         if (has_fixed_kernel(h->N, h->KP)) kind = KernelKind::kLane;
-      } else if (has_tiled(h->N, h->KP, mixed)) {
+      } else if (has_tiled(h, mixed)) {
         kind = KernelKind::kTile;
       }
     }
@@ -453,10 +462,11 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     g.n_tiles = 0;
     for (int k : kv.second) g.n_tiles += (hs[k]->n_ados + kPlanePad - 1) / kPlanePad;
     if (g.kind == KernelKind::kTile) {
-      const bool tile = tile_shape_info(g.N, g.KP, mixed, 0, nullptr, nullptr, nullptr, nullptr,
-                                        nullptr);
-      const bool wide = tile_shape_info(g.N, g.KP, mixed, kWideShape, nullptr, nullptr, nullptr,
-                                        nullptr, nullptr);
+      bool tile = true, wide = true;
+      for (int k : kv.second) {
+        tile = tile && shape_ok(hs[k], mixed, 0);
+        wide = wide && shape_ok(hs[k], mixed, kWideShape);
+      }
       if (tile) add_list(kv.second, kPlanePad, &g.begin[0], &g.count[0]);
       if (wide) {
         add_list(kv.second, 16, &g.begin[1], &g.count[1]);
@@ -590,7 +600,9 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
         *us = 1000.0 * static_cast<double>(ms) / (4 * kTuneReps);
         return rc;
       };
-      int rc = autotune_choose(device, mixed, g.N, g.KP, g.n_tiles, time_shape, &shape);
+      // A shape is available when the group carries the work list it uses.
+      auto available = [&](int s) { return g.count[g.list(s)] > 0; };
+      int rc = autotune_choose(device, mixed, g.N, g.KP, g.n_tiles, available, time_shape, &shape);
       if (rc) return rc;
     }
     g.shape = shape;

@@ -922,18 +922,28 @@ constexpr int kWideAdos = 16;
 constexpr int kWideWaves = 16;
 constexpr int kWideSlots = kWideWaves * (64 / kWideAdos);  // element slots per workgroup
 constexpr int kWideMaxN = 32;
+constexpr int kWideMaxKP = 4;  // modes per site (K + 1) the wide kernel is built for
+
+// Entry (r, c) of a packed ADO in the wide kernel's LDS tile: byte offsets
+// of its real and imaginary planes (the zero plane N*N for the imaginary part
+// of a diagonal entry; bit 31 of `im` set when the imaginary part is
+// negated, r > c), and H_rc.  One 16-byte read gives the commutator both.
+struct WideEntry {
+  uint32_t re, im;
+  double h;
+};
 
 // LDS layout of the wide kernel (byte offsets; every region 16-byte aligned).
 struct WideLds {
-  int x, h, nz, dec, dl, cr, ci, nu, up, dn, occ, pa, pb, x0, total;
+  int x, ent, nz, dec, dl, cr, ci, nu, up, dn, occ, pa, pb, x0, total;
 };
 __host__ __device__ inline int wide_align(int v) { return (v + 15) & ~15; }
 __host__ __device__ inline WideLds wide_lds(int N, int M, int s) {
   const int P = N * (N + 1) / 2;
   WideLds L;
   L.x = 0;                                                    // T [N*N + 1][kWideAdos]
-  L.h = wide_align(L.x + (N * N + 1) * kWideAdos * s);        // double [N*N]
-  L.nz = wide_align(L.h + N * N * 8);                         // uint32 [N] row masks
+  L.ent = wide_align(L.x + (N * N + 1) * kWideAdos * s);      // WideEntry [N*N]
+  L.nz = wide_align(L.ent + N * N * 16);                      // uint32 [N] row masks
   L.dec = wide_align(L.nz + N * 4);                           // double [N] (trap + rec) / 2
   L.dl = wide_align(L.dec + N * 8);                           // double [N] delta
   L.cr = wide_align(L.dl + N * 8);                            // double [M]
@@ -951,9 +961,10 @@ __host__ __device__ inline WideLds wide_lds(int N, int M, int s) {
 
 template <typename T>
 struct WideCtx {
-  int N, KP, t;
+  int N, t;
   const T *sx;
-  const double *sh, *sdec, *sdl, *scr, *sci;
+  const WideEntry *sent;
+  const double *sdec, *sdl, *scr, *sci;
   const uint32_t *snz;
   const int32_t *sup, *sdn;
   const uint8_t *socc;
@@ -962,98 +973,153 @@ struct WideCtx {
   const double *sx0;  // LDS copy of the FP64 sigma_0 stage input (FP32 storage)
   const HEOM_GLOBAL double *y0;
   HEOM_GLOBAL double *out0;
-  int64_t S, i;
+  uint32_t S;  // plane stride in ADOs; every buffer of a wide launch is below 4 GiB
+  int64_t i;
   double damp, coef;
 };
 
-// Element (a, b) of the lane's ADO: the operations of tile_load and
-// tile_finish with runtime a, b.  X0SRC reads sigma_0 from its FP64 copies.
-template <typename C, typename T, bool X0SRC>
-__device__ __forceinline__ void wide_element(const WideCtx<T> &c, int a, int b) {
-#pragma clang fp contract(off)
-  const int N = c.N, KP = c.KP, t = c.t;
-  const int E = ent_re(N, a, b);
-  const HEOM_GLOBAL T *pre = c.X + E * c.S;
-  const HEOM_GLOBAL T *pim = c.X + (E + 1) * c.S;
+// Global values one element needs: neighbour gathers along the modes of its
+// sites, and its state entry.
+template <typename C, int KP>
+struct WideLoads {
+  C yar[KP], yai[KP], ybr[KP], ybi[KP], zar[KP], zai[KP], zbr[KP], zbi[KP];
+  int jua[KP], jub[KP];
+  C str, sti;
+};
+
+// Plane of a tile byte offset (entry fields) and the tile's bytes per plane.
+template <typename T>
+__device__ __forceinline__ int wide_plane(uint32_t off) {
+  return static_cast<int>((off & 0x7fffffffu) / (kWideAdos * sizeof(T)));
+}
+
+// Phase 1 of element (a, b) of the lane's ADO (tile_load with runtime a, b):
+// every global load, at 32-bit byte offsets from the buffers' bases.  On the
+// diagonal the loads that the tile kernel skips read the element's own real
+// plane instead; their values are not used.  X0SRC reads sigma_0's state
+// from its FP64 copy.
+template <typename C, typename T, bool X0SRC, int KP>
+__device__ __forceinline__ void wide_load(const WideCtx<T> &c, int a, int b,
+                                          WideLoads<C, KP> &L) {
+  const int N = c.N, t = c.t;
+  const int E = wide_plane<T>(c.sent[a * N + b].re);
+  const bool offd = a != b;
+  const uint32_t Ei = offd ? E + 1 : E;  // a plane that exists
+  const uint32_t sz = static_cast<uint32_t>(sizeof(T));
+  const uint32_t pre = static_cast<uint32_t>(E) * c.S * sz;
+  const uint32_t pim = Ei * c.S * sz;
   const uint32_t self = static_cast<uint32_t>(c.i);
-  auto xe = [&](int e) -> C {
-    if constexpr (X0SRC)
+  auto off = [&](int j) -> uint32_t { return (j >= 0 ? static_cast<uint32_t>(j) : self) * sz; };
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int ma = a * KP + k, mb = b * KP + k;
+    L.jua[k] = c.sup[ma * kWideAdos + t];
+    L.jub[k] = c.sup[mb * kWideAdos + t];
+    const int jda = c.sdn[ma * kWideAdos + t], jdb = c.sdn[mb * kWideAdos + t];
+    const uint32_t oa = off(L.jua[k]), ob = off(L.jub[k]), da = off(jda), db = off(jdb);
+    L.yar[k] = static_cast<C>(ld_off(c.X, pre + oa));
+    L.yai[k] = static_cast<C>(ld_off(c.X, pim + oa));
+    L.ybr[k] = static_cast<C>(ld_off(c.X, pre + ob));
+    L.ybi[k] = static_cast<C>(ld_off(c.X, pim + ob));
+    L.zar[k] = static_cast<C>(ld_off(c.X, pre + da));
+    L.zai[k] = static_cast<C>(ld_off(c.X, pim + da));
+    L.zbr[k] = static_cast<C>(ld_off(c.X, pre + db));
+    L.zbi[k] = static_cast<C>(ld_off(c.X, pim + db));
+  }
+  L.sti = C(0);
+  if constexpr (X0SRC) {
+    L.str = static_cast<C>(c.y0[E]);
+    if (offd) L.sti = static_cast<C>(c.y0[E + 1]);
+  } else {
+    L.str = static_cast<C>(ld_off(c.Yp, pre + self * sz));
+    const C v = static_cast<C>(ld_off(c.Yp, pim + self * sz));
+    if (offd) L.sti = v;
+  }
+}
+
+// Phase 2 of element (a, b) (tile_finish with runtime a, b): the commutator
+// from LDS over the nonzero couplings in increasing k (negating an imaginary
+// part equals the tile kernel's multiplication by -1), then decay, bath
+// couplings, RK4 stage and store, in the tile kernel's order.
+template <typename C, typename T, bool X0SRC, int KP>
+__device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
+                                            const WideLoads<C, KP> &L) {
+#pragma clang fp contract(off)
+  const int N = c.N, t = c.t;
+  const char *sxt = reinterpret_cast<const char *>(c.sx) + t * sizeof(T);
+  auto xre = [&](uint32_t off) -> C {
+    if constexpr (X0SRC) {
+      const int e = wide_plane<T>(off);
       return e < N * N ? static_cast<C>(c.sx0[e]) : C(0);
-    else
-      return static_cast<C>(c.sx[e * kWideAdos + t]);
+    } else {
+      return static_cast<C>(*reinterpret_cast<const T *>(sxt + off));
+    }
   };
-  auto off = [&](int j) -> uint32_t {
-    return (j >= 0 ? static_cast<uint32_t>(j) : self) * static_cast<uint32_t>(sizeof(T));
+  auto xim = [&](uint32_t im) -> C {
+    const C v = xre(im & 0x7fffffffu);
+    return (im >> 31) ? -v : v;
   };
+  const WideEntry eab = c.sent[a * N + b];
+  const bool offd = a != b;
+  const WideEntry *rowA = c.sent + a * N;
+  const WideEntry *colB = c.sent + b;
   C sr = C(0), si = C(0);
   uint32_t mask = c.snz[a] | c.snz[b];
   while (mask) {
     const int k = __builtin_ctz(mask);
     mask &= mask - 1;
-    const C hak = static_cast<C>(c.sh[a * N + k]);
-    const C hkb = static_cast<C>(c.sh[k * N + b]);
-    const C xkb_r = xe(ent_re(N, k, b));
-    const C xkb_i = static_cast<C>(ent_sg(k, b)) * xe(ent_im(N, k, b));
-    const C xak_r = xe(ent_re(N, a, k));
-    const C xak_i = static_cast<C>(ent_sg(a, k)) * xe(ent_im(N, a, k));
+    const WideEntry eak = rowA[k];
+    const WideEntry ekb = colB[k * N];
+    const C hak = static_cast<C>(eak.h);
+    const C hkb = static_cast<C>(ekb.h);
+    const C xkb_r = xre(ekb.re);
+    const C xkb_i = xim(ekb.im);
+    const C xak_r = xre(eak.re);
+    const C xak_i = xim(eak.im);
     sr = fmad(-xak_r, hkb, fmad(hak, xkb_r, sr));
     si = fmad(-xak_i, hkb, fmad(hak, xkb_i, si));
   }
   C ar = si, ai = -sr;
-  const C xr = xe(E), xi = xe(ent_im(N, a, b));
+  const C xr = xre(eab.re), xi = xim(eab.im);
   C dec = static_cast<C>(c.damp) + static_cast<C>(c.sdec[a]) + static_cast<C>(c.sdec[b]);
-  if (a != b) dec += static_cast<C>(c.sdl[a]) + static_cast<C>(c.sdl[b]);
+  if (offd) dec += static_cast<C>(c.sdl[a]) + static_cast<C>(c.sdl[b]);
   ar = fmad(-dec, xr, ar);
   ai = fmad(-dec, xi, ai);
+#pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int ma = a * KP + k;
-    const int mb = b * KP + k;
-    if (a != b) {
-      const int ja = c.sup[ma * kWideAdos + t];
-      const int jb = c.sup[mb * kWideAdos + t];
-      const C yar = static_cast<C>(ld_off(pre, off(ja))), yai = static_cast<C>(ld_off(pim, off(ja)));
-      const C ybr = static_cast<C>(ld_off(pre, off(jb))), ybi = static_cast<C>(ld_off(pim, off(jb)));
-      const C fa = ja >= 0 ? C(1) : C(0);
-      const C fb = jb >= 0 ? C(1) : C(0);
-      ar = fmad(-fa, yai, fmad(fb, ybi, ar));
-      ai = fmad(-fb, ybr, fmad(fa, yar, ai));
+    const int ma = a * KP + k, mb = b * KP + k;
+    if (offd) {
+      const C fa = L.jua[k] >= 0 ? C(1) : C(0);
+      const C fb = L.jub[k] >= 0 ? C(1) : C(0);
+      ar = fmad(-fa, L.yai[k], fmad(fb, L.ybi[k], ar));
+      ai = fmad(-fb, L.ybr[k], fmad(fa, L.yar[k], ai));
     }
-    const int ja = c.sdn[ma * kWideAdos + t];
-    const int jb = c.sdn[mb * kWideAdos + t];
-    const C zar = static_cast<C>(ld_off(pre, off(ja)));
-    const C zbr = static_cast<C>(ld_off(pre, off(jb)));
-    const C zai = (a == b) ? C(0) : static_cast<C>(ld_off(pim, off(ja)));
-    const C zbi = (a == b) ? C(0) : static_cast<C>(ld_off(pim, off(jb)));
+    const C za_i = offd ? L.zai[k] : C(0);
+    const C zb_i = offd ? L.zbi[k] : C(0);
     const C na = static_cast<C>(c.socc[ma * kWideAdos + t]);
     const C nb = static_cast<C>(c.socc[mb * kWideAdos + t]);
     const C car = na * static_cast<C>(c.scr[ma]), cai = na * static_cast<C>(c.sci[ma]);
     const C cbr = nb * static_cast<C>(c.scr[mb]), cbi = nb * static_cast<C>(c.sci[mb]);
-    ar = fmad(-car, zai, fmad(-cai, zar, ar));
-    ai = fmad(-cai, zai, fmad(car, zar, ai));
-    ar = fmad(-cbi, zbr, fmad(cbr, zbi, ar));
-    ai = fmad(-cbi, zbi, fmad(-cbr, zbr, ai));
-  }
-  C str, sti = C(0);
-  const uint32_t oi = self * static_cast<uint32_t>(sizeof(T));
-  if constexpr (X0SRC) {
-    str = static_cast<C>(c.y0[E]);
-    if (a != b) sti = static_cast<C>(c.y0[E + 1]);
-  } else {
-    str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
-    if (a != b) sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
+    ar = fmad(-car, za_i, fmad(-cai, L.zar[k], ar));
+    ai = fmad(-cai, za_i, fmad(car, L.zar[k], ai));
+    ar = fmad(-cbi, L.zbr[k], fmad(cbr, zb_i, ar));
+    ai = fmad(-cbi, zb_i, fmad(-cbr, L.zbr[k], ai));
   }
   const C coef = static_cast<C>(c.coef);
-  const C nr = fmad(coef, ar, str);
-  const C ni = fmad(coef, ai, sti);
+  const C nr = fmad(coef, ar, L.str);
+  const C ni = fmad(coef, ai, L.sti);
+  const int E = wide_plane<T>(eab.re);
   if constexpr (X0SRC) {
     c.out0[E] = nr;
-    if (a != b) c.out0[E + 1] = ni;
+    if (offd) c.out0[E + 1] = ni;
   }
-  st_off(c.Out + E * c.S, oi, static_cast<T>(nr));
-  if (a != b) st_off(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
+  const uint32_t sz = static_cast<uint32_t>(sizeof(T));
+  const uint32_t oi = static_cast<uint32_t>(c.i) * sz;
+  st_off(c.Out, static_cast<uint32_t>(E) * c.S * sz + oi, static_cast<T>(nr));
+  if (offd) st_off(c.Out, static_cast<uint32_t>(E + 1) * c.S * sz + oi, static_cast<T>(ni));
 }
 
-template <typename T>
+template <typename T, int KP>
 __global__ void __launch_bounds__(64 * kWideWaves)
     stage_wide(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
                double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
@@ -1061,10 +1127,10 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   constexpr bool MIXED = sizeof(T) == 4;
   const WorkItem w = work[blockIdx.x];
   const InstDesc &d = descs[w.inst];
-  const int N = d.N, M = d.M, KP = d.KP, N2 = N * N, P = N * (N + 1) / 2;
+  const int N = d.N, M = d.M, N2 = N * N, P = N * (N + 1) / 2;
   const WideLds L = wide_lds(N, M, static_cast<int>(sizeof(T)));
   T *sx = reinterpret_cast<T *>(wide_smem + L.x);
-  double *sh = reinterpret_cast<double *>(wide_smem + L.h);
+  WideEntry *sent = reinterpret_cast<WideEntry *>(wide_smem + L.ent);
   uint32_t *snz = reinterpret_cast<uint32_t *>(wide_smem + L.nz);
   double *sdec = reinterpret_cast<double *>(wide_smem + L.dec);
   double *sdl = reinterpret_cast<double *>(wide_smem + L.dl);
@@ -1085,7 +1151,8 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   const HEOM_GLOBAL double *Pg = gmem(d.params);
   const ParamOffsets o = param_offsets(N, M);
   // Stage the tile (invalid ADOs of the last tile read ADO 0 and store 0),
-  // the parameters, the neighbour tables and the element map.
+  // the entry table with H, the parameters, the neighbour tables and the
+  // element map.
   for (int idx = tid; idx < N2 * kWideAdos; idx += blockDim.x) {
     const int e = idx / kWideAdos, t = idx % kWideAdos;
     const int64_t i = static_cast<int64_t>(w.first) + t;
@@ -1093,7 +1160,14 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     sx[idx] = i < d.n_ados ? v : T(0);
   }
   if (tid < kWideAdos) sx[N2 * kWideAdos + tid] = T(0);
-  for (int idx = tid; idx < N2; idx += blockDim.x) sh[idx] = Pg[o.h_re + idx];
+  constexpr uint32_t kPlaneBytes = kWideAdos * sizeof(T);
+  for (int idx = tid; idx < N2; idx += blockDim.x) {
+    const int r = idx / N, c = idx % N;
+    sent[idx] = WideEntry{static_cast<uint32_t>(ent_re(N, r, c)) * kPlaneBytes,
+                          static_cast<uint32_t>(ent_im(N, r, c)) * kPlaneBytes |
+                              (r > c ? 0x80000000u : 0u),
+                          Pg[o.h_re + idx]};
+  }
   for (int idx = tid; idx < N; idx += blockDim.x) {
     uint32_t m = 0;
     for (int k = 0; k < N; ++k)
@@ -1134,10 +1208,9 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     for (int m = 0; m < M; ++m)
       damp = fmad(static_cast<double>(socc[m * kWideAdos + tt]), snu[m], damp);
     return WideCtx<T>{N,
-                      KP,
                       tt,
                       sx,
-                      sh,
+                      sent,
                       sdec,
                       sdl,
                       scr,
@@ -1152,7 +1225,7 @@ __global__ void __launch_bounds__(64 * kWideWaves)
                       sx0,
                       gmem(bufs.y0),
                       gmem(bufs.out0),
-                      S,
+                      static_cast<uint32_t>(S),
                       ii,
                       damp,
                       coef};
@@ -1160,7 +1233,11 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   // With FP32 storage, sigma_0 is computed separately below, in FP64.
   if (i < d.n_ados && !(MIXED && i == 0)) {
     const WideCtx<T> ctx = make_ctx(t, i);
-    for (int p = slot; p < P; p += kWideSlots) wide_element<T, T, false>(ctx, spa[p], spb[p]);
+    for (int p = slot; p < P; p += kWideSlots) {
+      WideLoads<T, KP> Ld;
+      wide_load<T, T, false, KP>(ctx, spa[p], spb[p], Ld);
+      wide_finish<T, T, false, KP>(ctx, spa[p], spb[p], Ld);
+    }
     if (!MIXED && i == 0 && slot == 0)
       scalar_update(d, bufs, N, coef, [&](int e) { return static_cast<double>(sx[e * kWideAdos]); });
   }
@@ -1169,7 +1246,11 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     // whole workgroup of the first tile.
     if (w.first == 0) {
       const WideCtx<T> ctx0 = make_ctx(0, 0);
-      for (int p = tid; p < P; p += blockDim.x) wide_element<double, T, true>(ctx0, spa[p], spb[p]);
+      for (int p = tid; p < P; p += blockDim.x) {
+        WideLoads<double, KP> L0;
+        wide_load<double, T, true, KP>(ctx0, spa[p], spb[p], L0);
+        wide_finish<double, T, true, KP>(ctx0, spa[p], spb[p], L0);
+      }
       if (tid == 0) scalar_update(d, bufs, N, coef, [&](int e) { return sx0[e]; });
     }
   }

@@ -194,7 +194,9 @@ def test_tile_shapes_and_forced_shape_validation():
                     assert 1 <= waves <= 8
             for kp in (1, 2, 4):
                 info = heom.tile_shape_info(N, kp, prec, wide)
-                assert (info is not None) == (N <= 32), (N, kp, prec)
+                # LDS bound: with 4 modes per site, FP64 tiles of 32 sites do not fit.
+                fits = N <= 32 and not (N == 32 and kp == 4 and prec == "fp64")
+                assert (info is not None) == fits, (N, kp, prec)
                 if info is not None:
                     assert info[:2] == (16, 1024)
     assert lib.heom_tile_shape_info(7, 1, 0, count, None, None, None, None, None) == \
