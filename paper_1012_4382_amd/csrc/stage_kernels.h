@@ -163,6 +163,40 @@ __device__ __forceinline__ void scalar_update(const InstDesc &d, const StageBufs
   b.outs[2] = fmad(coef, xq, y_q);
 }
 
+// Sum over the 64 lanes of a wave, by a butterfly of lane shuffles (every
+// lane ends with the same value; the order of additions is fixed).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// scalar_update for the LDS-tiled kernels, run by a whole wave with every
+// lane active: lane s forms site s's terms of the trap and recombination
+// fluxes, and the wave reduces them with shuffles.
+template <typename LoadX>
+__device__ __forceinline__ void scalar_update_wave(const InstDesc &d, const StageBufs &b, int N,
+                                                   double coef, int lane, LoadX x0e) {
+#pragma clang fp contract(off)
+  const ParamOffsets o = param_offsets(N, d.M);
+  double ft = 0.0, fr = 0.0;
+  for (int s = lane; s < N; s += 64) {
+    const double pop = x0e(s);
+    ft = fmad(d.params[o.trap + s], pop, ft);
+    fr = fmad(d.params[o.rec + s], pop, fr);
+  }
+  ft = wave_sum(ft);
+  fr = wave_sum(fr);
+  if (lane == 0) {
+    const double xq = b.xs[0];
+    const double y_t = b.ys[0], y_r = b.ys[1], y_q = b.ys[2];
+    b.outs[0] = fmad(coef, ft, y_t);
+    b.outs[1] = fmad(coef, fr, y_r);
+    b.outs[2] = fmad(coef, xq, y_q);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Specialised kernel: compile-time N and modes per site, real Hamiltonian.
 // ---------------------------------------------------------------------------
@@ -863,6 +897,16 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
     }
   }
   __syncthreads();
+  // Sink fluxes and scalars of sigma_0: wave 0 of the first tile, every lane
+  // still active.
+  if (w.first == 0 && wave == 0) {
+    scalar_update_wave(d, bufs, N, coef, lane, [&](int s) {
+      if constexpr (MIXED)
+        return sx0[s];
+      else
+        return static_cast<double>(sx[s * kTile]);
+    });
+  }
   if (!valid) return;  // no barrier below
   const HEOM_CONST double *P = cmem(d.params);
   double damp = 0.0;
@@ -891,14 +935,6 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
     // sigma_0 again, in FP64 from its FP64 copy; these writes follow the FP32
     // ones above in program order, so they are the ones that remain.
     if (is0) tile_dispatch<N, KP, W, CH0, double, T, true>(wave, ctx);
-  }
-  if (is0 && wave == 0) {
-    scalar_update(d, bufs, N, coef, [&](int s) {
-      if constexpr (MIXED)
-        return sx0[s];
-      else
-        return static_cast<double>(sx[s * kTile + lane]);
-    });
   }
 }
 
@@ -1198,6 +1234,15 @@ __global__ void __launch_bounds__(64 * kWideWaves)
       for (int e = tid; e < N2; e += blockDim.x) sx0[e] = bufs.x0[e];
   }
   __syncthreads();
+  // Sink fluxes and scalars of sigma_0: wave 0 of the first tile.
+  if (w.first == 0 && tid < 64) {
+    scalar_update_wave(d, bufs, N, coef, tid, [&](int e) {
+      if constexpr (MIXED)
+        return sx0[e];
+      else
+        return static_cast<double>(sx[e * kWideAdos]);
+    });
+  }
 
   const int lane = tid & 63;
   const int t = lane % kWideAdos;
@@ -1238,8 +1283,6 @@ __global__ void __launch_bounds__(64 * kWideWaves)
       wide_load<T, T, false, KP>(ctx, spa[p], spb[p], Ld);
       wide_finish<T, T, false, KP>(ctx, spa[p], spb[p], Ld);
     }
-    if (!MIXED && i == 0 && slot == 0)
-      scalar_update(d, bufs, N, coef, [&](int e) { return static_cast<double>(sx[e * kWideAdos]); });
   }
   if constexpr (MIXED) {
     // sigma_0 in FP64 from its FP64 copies, its elements spread over the
@@ -1251,7 +1294,6 @@ __global__ void __launch_bounds__(64 * kWideWaves)
         wide_load<double, T, true, KP>(ctx0, spa[p], spb[p], L0);
         wide_finish<double, T, true, KP>(ctx0, spa[p], spb[p], L0);
       }
-      if (tid == 0) scalar_update(d, bufs, N, coef, [&](int e) { return sx0[e]; });
     }
   }
 }
