@@ -35,6 +35,37 @@ def dimer() -> dict:
     return dict(system=system(DIMER_H), depth=4, rho0=site_state(2, 1), dt=1.0, steps=1000)
 
 
+# Table 1 of the paper (label tab:tab1): the FMO exciton Hamiltonian in the
+# site basis, BChl 1..7, cm^-1.
+FMO_TABLE1_H = np.array([
+    [12410.0, -87.7, 5.5, -5.9, 6.7, -13.7, -9.9],
+    [-87.7, 12530.0, 30.8, 8.2, 0.7, 11.8, 4.3],
+    [5.5, 30.8, 12210.0, -53.5, -2.2, -9.6, 6.0],
+    [-5.9, 8.2, -53.5, 12320.0, -70.7, -17.0, -63.3],
+    [6.7, 0.7, -2.2, -70.7, 12480.0, 81.1, -1.3],
+    [-13.7, 11.8, -9.6, -17.0, 81.1, 12630.0, 39.7],
+    [-9.9, 4.3, 6.0, -63.3, -1.3, 39.7, 12440.0],
+])
+
+
+def fmo_table1(lam: float = 35.0, gamma_inv_fs: float = 166.0, T: float = 300.0,
+               trap_sites=(3, 4), trap_inv_ps: float = 2.5, rec_inv_ps: float = 250.0,
+               theta_form: int = 0, sinks: bool = True) -> dict:
+    """The paper's FMO model (section on trapping times): Table 1 Hamiltonian,
+    identical Drude-Lorentz baths (lambda, 1/gamma) at T, K = 0 with the
+    correction on; trapping from BChl 3 and 4 with 1/Gamma_RC = 2.5 ps and
+    radiative decay from every site with 1/Gamma_phot = 250 ps (sinks=False:
+    the isolated complex)."""
+    trap = rec = None
+    if sinks:
+        trap = np.zeros(7)
+        for s in trap_sites:
+            trap[s - 1] = 1.0 / trap_inv_ps
+        rec = np.full(7, 1.0 / rec_inv_ps)
+    return system(FMO_TABLE1_H, lam=lam, gamma_inv_fs=gamma_inv_fs, T=T, trap=trap, rec=rec,
+                  theta_form=theta_form)
+
+
 def fmo_like_hamiltonian(rng, N: int = 7) -> np.ndarray:
     """Draw order: site energies uniform(12200, 12600, N); then for i < j in
     row-major order J_ij = normal(0, 60) * exp(-|i - j| / 2); real symmetric."""
