@@ -117,6 +117,10 @@ def library():
     """Loads libheom.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # PyTorch's HIP runtime is loaded first, so that the library binds to
+        # the same runtime instance that allocates the workspaces and streams.
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1012_4382_amd.build`")

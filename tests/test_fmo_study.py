@@ -30,11 +30,17 @@ def test_converge_depth_stops_at_the_criterion():
                 "t_end_fs": 1.0, "p_recomb": 0.0, "p_remaining": 0.0}
 
     r = fmo_study.converge_depth(run, 3, 20.0, 12)
-    # |t(D+1) - t(D)| = 400 / 2^D <= 20 first at D = 5 -> result at depth 6.
-    assert r["converged"] and r["depth"] == 6 and calls == [3, 4, 5, 6]
-    assert r["delta_fs"] == 800.0 / 2 ** 6
+    # |t(D+1) - t(D)| = 400 / 2^D: 25 (4->5), 12.5 (5->6), 6.25 (6->7): two
+    # changes in a row within 20 fs end the search at depth 7.
+    assert r["converged"] and r["depth"] == 7 and calls == [3, 4, 5, 6, 7]
+    assert r["delta_fs"] == 400.0 / 2 ** 6
     r = fmo_study.converge_depth(run, 3, 1e-9, 5)
     assert not r["converged"] and r["depth"] == 5
+
+    # A chance agreement of two shallow depths does not end the search.
+    seq = {3: 7000.0, 4: 7005.0, 5: 6500.0, 6: 6490.0, 7: 6485.0}
+    r = fmo_study.converge_depth(lambda d: {"mean_trap_time_fs": seq[d]}, 3, 20.0, 7)
+    assert r["converged"] and r["depth"] == 7
 
 
 def test_gibbs_populations_limits():
