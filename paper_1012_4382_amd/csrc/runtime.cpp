@@ -2,7 +2,7 @@
 //
 // Builds hierarchies (params.cpp, hierarchy.cpp), lays out caller-owned device
 // workspaces, uploads per-instance parameters and neighbour tables, and
-// sequences the RK4 stage kernels (stage_kernels.hip) with the sigma_0
+// sequences the RK4 stage kernels (stage_kernels.h) with the sigma_0
 // history ring that is copied to the host in chunks (the paper keeps every
 // ADO on the device and moves only the N x N reduced density matrix,
 // Appendix B).
@@ -22,7 +22,7 @@
 
 namespace heom {
 
-// stage_kernels.hip
+// kernels_dispatch.hip
 bool has_fixed_kernel(int N, int KP);
 hipError_t prepare_wide(int N, int M, bool mixed);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,

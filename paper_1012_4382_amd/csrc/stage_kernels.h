@@ -2,7 +2,6 @@
 // included by the kernels_*.hip translation units, which instantiate and
 // launch them (split so that the build compiles them in parallel).
 //
-//
 // One launch evaluates the right-hand side of eq:lab8 (paper, Appendix A) for
 // every ADO of a set of instances and applies one RK4 stage to it.
 //
@@ -31,17 +30,20 @@
 // shallower neighbours.  Every ADO is Hermitian, so only the upper triangle is
 // stored (N*N reals per ADO, see heom_internal.h).
 //
-// Lane mapping: one lane per ADO, consecutive lanes on consecutive ADOs.  Each
-// element of the stored state is a plane over ADOs, so every self access of a
-// wave is one contiguous 512-byte (FP64) segment, and neighbour gathers (whose
-// indices are nearly consecutive in the lexicographic order of the hierarchy)
-// touch few cache lines.  The ADO of sigma_0 (lane 0 of its instance) also
-// integrates the sink populations and writes the history record.
+// Lane mapping: consecutive lanes on consecutive ADOs.  Each element of the
+// stored state is a plane over ADOs, so a wave's access to one element of its
+// ADOs is a contiguous segment, and neighbour gathers (whose indices are
+// nearly consecutive in the lexicographic order of the hierarchy) touch few
+// cache lines.  The sigma_0 part of each stage (sink fluxes, P_trap, P_rec, Q)
+// is done where ADO 0 is; history records are written by the snapshot kernel.
 //
-// Two kernels:
-//  * stage_fixed<N, KP>: N <= 8 sites, K+1 = KP modes per site, real H.  The
-//    ADO's N*N reals live in registers, every loop is unrolled at compile time
-//    and H, c, nu are wave-uniform scalar loads.
+// Kernels:
+//  * stage_tile<N, KP, T, shape> (N <= 12, real H): 64-ADO tiles in LDS,
+//    compile-time element groups per wave; the default.
+//  * stage_wide<T, KP> (N <= 32, real H): 16-ADO tiles in LDS, runtime N;
+//    launch shape 5 of the same family (the autotuner chooses).
+//  * stage_fixed<N, KP> (N <= 8, real H): one lane per ADO with the ADO's N*N
+//    reals in registers; a diagnostic alternative.
 //  * stage_generic: any N <= 64, any K, complex H; reads the stage input
 //    straight from the planes (all such reads are coalesced across lanes).
 #pragma once
@@ -543,7 +545,7 @@ __global__ void __launch_bounds__(256) stage_generic(const InstDesc *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernel: compile-time N <= 8 and modes per site, real Hamiltonian.
+// Tile kernel: compile-time N <= 12 and modes per site, real Hamiltonian.
 // A workgroup stages the stage input of 64 consecutive ADOs (one "tile") and
 // their neighbour tables in LDS; wave w then produces the packed elements
 // p = w, w + W, w + 2W, ... for all 64 ADOs.  Each wave's element group is
