@@ -72,6 +72,8 @@ def _parse():
                    help="skip the HBM-resident N=7, depth-16 measurement")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 256 MiB device copy (reference for traffic counters)")
+    p.add_argument("--no-batch-scaling", action="store_true",
+                   help="skip the 16-128 solve batches of the benchmarked workload")
     p.add_argument("--no-sweep", action="store_true",
                    help="skip the 64-instance parameter-sweep measurement")
     p.add_argument("--serve", type=int, default=40, metavar="R",
@@ -240,6 +242,45 @@ def _wide_sizing(heom, torch, workloads, stream, kernel):
     return out
 
 
+def _batch_scaling(heom, torch, workloads, stream, kernel, sizes=(16, 32, 64, 128)):
+    """The benchmarked workload with more solves per launch sequence (seeds
+    0..n/2-1, sites 1 and 6): where the stage kernel leaves the latency-bound
+    regime of a few hundred tiles.  Beside it, a plain 1 GiB device copy, the
+    bandwidth a kernel that only streams can reach on this GPU."""
+    rows = []
+    for n in sizes:
+        batch = workloads.fmo_like_batch(seeds=tuple(range(n // 2)), steps=200)
+        hs = [heom.Hierarchy(w["system"], w["depth"]) for w in batch]
+        r0 = [w["rho0"] for w in batch]
+        row = {"solves": n, "n_ados": sum(h.n_ados for h in hs)}
+        for prec, s in (("fp64", 8), ("fp32", 4)):
+            k_ms, rate = _stage_kernel_timing(heom, torch, hs, r0, stream, kernel, prec,
+                                              steps=100)
+            bpl = row["n_ados"] * (11.0 / 4.0) * hs[0].N * hs[0].N * s
+            row[prec] = {"ado_steps_per_s": rate, "kernel_avg_us": k_ms * 1e3,
+                         "achieved_GBps": bpl / (k_ms * 1e-3) / 1e9,
+                         "frac_of_hbm_peak": bpl / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        rows.append(row)
+        for h in hs:
+            h.close()
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            dst.copy_(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(20):
+            dst.copy_(src)
+        ev1.record(stream)
+    ev1.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 20 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    return {"workload": "fmo_like_7site_depth7_n_solves", "rows": rows,
+            "device_copy_1GiB_GBps": copy_gbs,
+            "device_copy_frac_of_hbm_peak": copy_gbs / HBM_PEAK_GBS}
+
+
 def _cpu_baseline(w, target_s=12.0):
     """The oracle (as it stands) on this host, on a bounded sample of one solve."""
     import oracle
@@ -367,6 +408,8 @@ def main():
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
         result["wide_sizing"] = _wide_sizing(heom, torch, workloads, stream, args.kernel)
+    if not args.no_batch_scaling:
+        result["batch_scaling"] = _batch_scaling(heom, torch, workloads, stream, args.kernel)
     if not args.no_sweep:
         result["sweep"] = _sweep(heom, torch, workloads, stream)
     if not args.no_variants:

@@ -47,8 +47,10 @@ HEOM_HD inline int pair_index(int N, int a, int b) {  // a < b
 //   [.., +M)           Im c_m
 //   [.., +M)           nu_m
 //   [.., +N*N)         packed rho0 (used by the initialisation kernel)
+//   [.., +ceil(R/2))   FP32 copy of the first R = rho0 entries, two floats
+//                      per double (read by the FP32 stage kernels)
 struct ParamOffsets {
-  int h_re, h_im, half_gamma, delta, trap, rec, c_re, c_im, nu, rho0, total;
+  int h_re, h_im, half_gamma, delta, trap, rec, c_re, c_im, nu, rho0, f32, total;
 };
 HEOM_HD inline ParamOffsets param_offsets(int N, int M) {
   ParamOffsets o;
@@ -62,7 +64,8 @@ HEOM_HD inline ParamOffsets param_offsets(int N, int M) {
   o.c_im = o.c_re + M;
   o.nu = o.c_im + M;
   o.rho0 = o.nu + M;
-  o.total = o.rho0 + N * N;
+  o.f32 = o.rho0 + N * N;
+  o.total = o.f32 + (o.rho0 + 1) / 2;
   return o;
 }
 

@@ -154,6 +154,13 @@ int build_params(const heom_system *sys, heom_hierarchy *h) {
     h->params[o.c_im + m] = h->c_im[m];
     h->params[o.nu + m] = h->nu[m];
   }
+  // FP32 copy: each value rounded once here, as the FP32 kernels would round
+  // it on use.
+  unsigned char *f32 = reinterpret_cast<unsigned char *>(h->params.data() + o.f32);
+  for (int q = 0; q < o.rho0; ++q) {
+    const float v = static_cast<float>(h->params[q]);
+    std::memcpy(f32 + sizeof(float) * q, &v, sizeof(float));
+  }
   return HEOM_OK;
 }
 

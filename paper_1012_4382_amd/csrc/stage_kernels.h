@@ -80,6 +80,9 @@ __device__ __forceinline__ HEOM_GLOBAL T *gmem(T *p) {
 __device__ __forceinline__ const HEOM_CONST double *cmem(const double *p) {
   return (const HEOM_CONST double *)p;
 }
+__device__ __forceinline__ const HEOM_CONST float *cmem(const float *p) {
+  return (const HEOM_CONST float *)p;
+}
 // Load / store at a 32-bit per-lane byte offset from a wave-uniform base, so
 // that the address is one VGPR added to a scalar base (no 64-bit arithmetic
 // per lane).  Every plane, table and state buffer is far below 4 GiB.
@@ -640,6 +643,7 @@ __host__ __device__ constexpr int tile_waves(int N, bool fp64, int s) {
 template <typename T>
 struct TileCtx {
   const HEOM_CONST double *P;         // parameter block
+  const HEOM_CONST float *P32;        // its FP32 copy (same offsets)
   const T *sx;                        // LDS tile of the stage input, [N*N + 1][64]
   const int32_t *sup, *sdn;
   const uint8_t *socc;                // LDS neighbour tables, [M][64]
@@ -647,12 +651,25 @@ struct TileCtx {
   const HEOM_GLOBAL T *Yp;            // state planes
   HEOM_GLOBAL T *Out;                 // output planes
   const double *sx0;                  // LDS copy of the FP64 sigma_0 stage input (mixed)
+  const double *sf0;                  // the same, unpacked: Re [N*N], Im [N*N], and H_re
+                                      // [N*N] (mixed, first tile only)
   const HEOM_GLOBAL double *y0;       // FP64 sigma_0 state (mixed precision)
-  HEOM_GLOBAL double *out0;
+  HEOM_GLOBAL double *out0;           // FP64 sigma_0 output (mixed precision)
   int64_t S, i;
   int lane;
   double damp, coef;
 };
+
+// Parameter q in the arithmetic type C: FP32 arithmetic reads the FP32 copy
+// (the value a conversion on use would give, without the conversion and with
+// half the scalar registers).
+template <typename C, typename T>
+__device__ __forceinline__ C par(const TileCtx<T> &c, int q) {
+  if constexpr (sizeof(C) == 4)
+    return c.P32[q];
+  else
+    return c.P[q];
+}
 
 // Values of one element (A, B) read from global memory: the same element of
 // the deeper (y*) and shallower (z*) neighbours along the modes of sites A
@@ -668,8 +685,8 @@ struct ElemLoads {
 // branch-free: a missing neighbour (index -1) reads the lane's own entry and
 // is weighted by zero (the occupation is zero exactly where the shallower
 // neighbour is missing), so the loads of all elements of a wave are in
-// flight together.  X0SRC reads the state from the FP64 copy of sigma_0.
-template <int N, int KP, int A, int B, typename C, typename T, bool X0SRC>
+// flight together.
+template <int N, int KP, int A, int B, typename C, typename T>
 __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> &L) {
   constexpr int E = ent_re(N, A, B);
   const int lane = c.lane;
@@ -701,19 +718,14 @@ __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> 
       L.zbi[k] = static_cast<C>(ld_off(pim, ob));
     }
   }
-  if constexpr (X0SRC) {
-    L.str = static_cast<C>(c.y0[E]);
-    if constexpr (A != B) L.sti = static_cast<C>(c.y0[E + 1]);
-  } else {
-    const uint32_t oi = self * sizeof(T);
-    L.str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
-    if constexpr (A != B) L.sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
-  }
+  const uint32_t oi = self * sizeof(T);
+  L.str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
+  if constexpr (A != B) L.sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
 }
 
 // Phase 2 of element (A, B): right-hand side from the LDS tile and the loaded
 // values, RK4 stage update, store.  C is the arithmetic type.
-template <int N, int KP, int A, int B, typename C, typename T, bool X0SRC>
+template <int N, int KP, int A, int B, typename C, typename T>
 __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads<C, KP> &L) {
 #pragma clang fp contract(off)
   constexpr int M = N * KP;
@@ -721,18 +733,13 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
                 o_ci = 2 * N * N + 4 * N + M;
   constexpr int E = ent_re(N, A, B);
   const int lane = c.lane;
-  auto xe = [&](int e) -> C {
-    if constexpr (X0SRC)
-      return e < N * N ? static_cast<C>(c.sx0[e]) : C(0);
-    else
-      return static_cast<C>(c.sx[e * kTile + lane]);
-  };
+  auto xe = [&](int e) -> C { return static_cast<C>(c.sx[e * kTile + lane]); };
   // Coherent part: s = sum_k H_Ak X_kB - X_Ak H_kB; contribution -i s.
   C sr = C(0), si = C(0);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const C hak = static_cast<C>(c.P[A * N + k]);
-    const C hkb = static_cast<C>(c.P[k * N + B]);
+    const C hak = par<C>(c, A * N + k);
+    const C hkb = par<C>(c, k * N + B);
     const C xkb_r = xe(ent_re(N, k, B));
     const C xkb_i = static_cast<C>(ent_sg(k, B)) * xe(ent_im(N, k, B));
     const C xak_r = xe(ent_re(N, A, k));
@@ -742,8 +749,8 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
   }
   C ar = si, ai = -sr;
   const C xr = xe(E), xi = xe(ent_im(N, A, B));
-  C dec = static_cast<C>(c.damp) + static_cast<C>(c.P[o_hg + A]) + static_cast<C>(c.P[o_hg + B]);
-  if constexpr (A != B) dec += static_cast<C>(c.P[o_dl + A]) + static_cast<C>(c.P[o_dl + B]);
+  C dec = static_cast<C>(c.damp) + par<C>(c, o_hg + A) + par<C>(c, o_hg + B);
+  if constexpr (A != B) dec += par<C>(c, o_dl + A) + par<C>(c, o_dl + B);
   ar = fmad(-dec, xr, ar);
   ai = fmad(-dec, xi, ai);
 #pragma unroll
@@ -761,8 +768,8 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
     // Shallower neighbours: + i n c Z (site A) - i n conj(c) Z (site B).
     const C na = static_cast<C>(c.socc[ma * kTile + lane]);
     const C nb = static_cast<C>(c.socc[mb * kTile + lane]);
-    const C car = na * static_cast<C>(c.P[o_cr + ma]), cai = na * static_cast<C>(c.P[o_ci + ma]);
-    const C cbr = nb * static_cast<C>(c.P[o_cr + mb]), cbi = nb * static_cast<C>(c.P[o_ci + mb]);
+    const C car = na * par<C>(c, o_cr + ma), cai = na * par<C>(c, o_ci + ma);
+    const C cbr = nb * par<C>(c, o_cr + mb), cbi = nb * par<C>(c, o_ci + mb);
     const C zai = (A == B) ? C(0) : L.zai[k];
     const C zbi = (A == B) ? C(0) : L.zbi[k];
     // i (car + i cai) z_a = -(cai zar + car zai) + i (car zar - cai zai)
@@ -777,10 +784,8 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
   const C coef = static_cast<C>(c.coef);
   const C nr = fmad(coef, ar, L.str);
   const C ni = fmad(coef, ai, (A == B) ? C(0) : L.sti);
-  if constexpr (X0SRC) {
-    c.out0[E] = nr;
-    if constexpr (A != B) c.out0[E + 1] = ni;
-  }
+  // In FP32-mixed runs sigma_0 is written by tile_sigma0 alone.
+  if (sizeof(T) == 4 && c.i == 0) return;
   const uint32_t oi = static_cast<uint32_t>(c.i) * sizeof(T);
   st_off(c.Out + E * c.S, oi, static_cast<T>(nr));
   if constexpr (A != B) st_off(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
@@ -788,18 +793,16 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
 
 // One chunk of wave G's elements (element indices OFF + K): all global loads
 // first, then arithmetic and stores.
-template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool X0SRC, int... K>
+template <int N, int KP, int G, int W, int OFF, typename C, typename T, int... K>
 __device__ __forceinline__ void tile_chunk(const TileCtx<T> &c, std::integer_sequence<int, K...>) {
   ElemLoads<C, KP> L[sizeof...(K)];
-  (tile_load<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, X0SRC>(
-       c, L[K]),
+  (tile_load<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T>(c, L[K]),
    ...);
-  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, X0SRC>(
-       c, L[K]),
+  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T>(c, L[K]),
    ...);
 }
 
-template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T, bool X0SRC>
+template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T>
 __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int P = N * (N + 1) / 2;
   constexpr int count = (P - G + W - 1) / W;
@@ -808,25 +811,123 @@ __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int CH = CH0 / KP > 0 ? CH0 / KP : 1;
   if constexpr (OFF < count) {
     constexpr int len = (count - OFF < CH) ? count - OFF : CH;
-    tile_chunk<N, KP, G, W, OFF, C, T, X0SRC>(c, std::make_integer_sequence<int, len>{});
+    tile_chunk<N, KP, G, W, OFF, C, T>(c, std::make_integer_sequence<int, len>{});
     // Keep the next chunk's LDS reads from being hoisted above this chunk
     // (they cannot alias its global stores), which would hold every operand
     // of the wave's elements in registers at once.
 #if HEOM_TILE_CHUNK_BARRIER
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T, X0SRC>(c);
+    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T>(c);
   }
 }
 
 // Elements G, G + W, ... of every ADO of the tile (wave G of W).
-template <int N, int KP, int W, int CH0, typename C, typename T, bool X0SRC, int G = 0>
+template <int N, int KP, int W, int CH0, typename C, typename T, int G = 0>
 __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
   if constexpr (G < W) {
     if (wave == G)
-      tile_chunks<N, KP, G, W, CH0, 0, C, T, X0SRC>(c);
+      tile_chunks<N, KP, G, W, CH0, 0, C, T>(c);
     else
-      tile_dispatch<N, KP, W, CH0, C, T, X0SRC, G + 1>(wave, c);
+      tile_dispatch<N, KP, W, CH0, C, T, G + 1>(wave, c);
+  }
+}
+
+// sigma_0 of an FP32-mixed run, in FP64 (packed element p, chosen at run
+// time, so that one lane per element covers sigma_0): the right-hand side
+// from the FP64 copy of the stage input (LDS), the FP32 neighbour planes and
+// the FP64 state, with the operations of tile_finish in the same order, so
+// the result does not depend on the launch shape.  It is the only writer of
+// sigma_0, in both the FP64 copy and the FP32 planes.  Keeping this pass out
+// of the unrolled element code keeps FP64 operands out of the register
+// allocation of the FP32 kernel.
+template <int N, int KP, typename T>
+__device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
+#pragma clang fp contract(off)
+  constexpr int M = N * KP;
+  constexpr int o_hg = 2 * N * N, o_dl = 2 * N * N + N, o_cr = 2 * N * N + 4 * N,
+                o_ci = 2 * N * N + 4 * N + M, o_nu = 2 * N * N + 4 * N + 2 * M;
+  const int A = elem_a(N, p), B = elem_b(N, p);
+  const bool off = A != B;
+  const int E = ent_re(N, A, B);
+  const HEOM_GLOBAL T *pre = c.X + E * c.S;
+  const HEOM_GLOBAL T *pim = c.X + (E + 1) * c.S;
+  // Loads, as tile_load issues them for ADO 0 (entry 0 of the LDS tables; a
+  // missing neighbour reads ADO 0 itself and is weighted by zero).
+  double yar[KP], yai[KP], ybr[KP], ybi[KP], zar[KP], zai[KP], zbr[KP], zbi[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int ma = A * KP + k, mb = B * KP + k;
+    yar[k] = yai[k] = ybr[k] = ybi[k] = zai[k] = zbi[k] = 0.0;
+    if (off) {
+      const int ja = c.sup[ma * kTile], jb = c.sup[mb * kTile];
+      const uint32_t oa = static_cast<uint32_t>(ja >= 0 ? ja : 0) * sizeof(T);
+      const uint32_t ob = static_cast<uint32_t>(jb >= 0 ? jb : 0) * sizeof(T);
+      yar[k] = ld_off(pre, oa);
+      yai[k] = ld_off(pim, oa);
+      ybr[k] = ld_off(pre, ob);
+      ybi[k] = ld_off(pim, ob);
+    }
+    const int ja = c.sdn[ma * kTile], jb = c.sdn[mb * kTile];
+    const uint32_t oa = static_cast<uint32_t>(ja >= 0 ? ja : 0) * sizeof(T);
+    const uint32_t ob = static_cast<uint32_t>(jb >= 0 ? jb : 0) * sizeof(T);
+    zar[k] = ld_off(pre, oa);
+    zbr[k] = ld_off(pre, ob);
+    if (off) {
+      zai[k] = ld_off(pim, oa);
+      zbi[k] = ld_off(pim, ob);
+    }
+  }
+  const double str = c.y0[E];
+  const double sti = off ? c.y0[E + 1] : 0.0;
+  // Entries of the unpacked copy are the packed values with the sign of the
+  // imaginary part applied (+0 for the diagonal), as tile_finish forms them.
+  const double *Xr = c.sf0, *Xi = c.sf0 + N * N, *Hr = c.sf0 + 2 * N * N;
+  double sr = 0.0, si = 0.0;
+  // Not unrolled: this pass must not raise the kernel's register count
+  // above that of the element code.
+#pragma nounroll
+  for (int k = 0; k < N; ++k) {
+    const double hak = Hr[A * N + k];
+    const double hkb = Hr[k * N + B];
+    sr = fmad(-Xr[A * N + k], hkb, fmad(hak, Xr[k * N + B], sr));
+    si = fmad(-Xi[A * N + k], hkb, fmad(hak, Xi[k * N + B], si));
+  }
+  double ar = si, ai = -sr;
+  const double xr = Xr[A * N + B], xi = Xi[A * N + B];
+  double damp = 0.0;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    damp = fmad(static_cast<double>(c.socc[m * kTile]), c.P[o_nu + m], damp);
+  double dec = damp + c.P[o_hg + A] + c.P[o_hg + B];
+  if (off) dec += c.P[o_dl + A] + c.P[o_dl + B];
+  ar = fmad(-dec, xr, ar);
+  ai = fmad(-dec, xi, ai);
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int ma = A * KP + k, mb = B * KP + k;
+    if (off) {
+      const double fa = c.sup[ma * kTile] >= 0 ? 1.0 : 0.0;
+      const double fb = c.sup[mb * kTile] >= 0 ? 1.0 : 0.0;
+      ar = fmad(-fa, yai[k], fmad(fb, ybi[k], ar));
+      ai = fmad(-fb, ybr[k], fmad(fa, yar[k], ai));
+    }
+    const double na = static_cast<double>(c.socc[ma * kTile]);
+    const double nb = static_cast<double>(c.socc[mb * kTile]);
+    const double car = na * c.P[o_cr + ma], cai = na * c.P[o_ci + ma];
+    const double cbr = nb * c.P[o_cr + mb], cbi = nb * c.P[o_ci + mb];
+    ar = fmad(-car, zai[k], fmad(-cai, zar[k], ar));
+    ai = fmad(-cai, zai[k], fmad(car, zar[k], ai));
+    ar = fmad(-cbi, zbr[k], fmad(cbr, zbi[k], ar));
+    ai = fmad(-cbi, zbi[k], fmad(-cbr, zbr[k], ai));
+  }
+  const double nr = fmad(c.coef, ar, str);
+  const double ni = fmad(c.coef, ai, sti);
+  c.out0[E] = nr;
+  c.Out[E * c.S] = static_cast<T>(nr);
+  if (off) {
+    c.out0[E + 1] = ni;
+    c.Out[(E + 1) * c.S] = static_cast<T>(ni);
   }
 }
 
@@ -842,6 +943,7 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   constexpr bool MIXED = sizeof(T) == 4;
   __shared__ T sx[(N2 + 1) * kTile];
   __shared__ double sx0[MIXED ? N2 : 1];  // FP64 sigma_0 stage input, tile of ADO 0 only
+  __shared__ double sf0[MIXED ? 3 * N2 : 1];  // its unpacked form and H_re, tile of ADO 0
   __shared__ int32_t sup[M * kTile];
   __shared__ int32_t sdn[M * kTile];
   __shared__ uint8_t socc[M * kTile];
@@ -887,7 +989,15 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   if (wave == 0) sx[N2 * kTile + lane] = T(0);
   if constexpr (MIXED) {
     if (w.first == 0)
-      for (int e = threadIdx.x; e < N2; e += blockDim.x) sx0[e] = bufs.x0[e];
+      for (int e = threadIdx.x; e < N2; e += blockDim.x) {
+        const int r = e / N, q = e % N;
+        const double re = bufs.x0[ent_re(N, r, q)];
+        const double im = r == q ? 0.0 : bufs.x0[ent_im(N, r, q)];
+        sx0[e] = bufs.x0[e];
+        sf0[e] = re;
+        sf0[N2 + e] = static_cast<double>(ent_sg(r, q)) * im;
+        sf0[2 * N2 + e] = d.params[e];
+      }
   }
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
@@ -909,13 +1019,9 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
         return static_cast<double>(sx[s * kTile]);
     });
   }
-  if (!valid) return;  // no barrier below
   const HEOM_CONST double *P = cmem(d.params);
-  double damp = 0.0;
-#pragma unroll
-  for (int m = 0; m < M; ++m)
-    damp = fmad(static_cast<double>(socc[m * kTile + lane]), P[2 * N * N + 4 * N + 2 * M + m], damp);
   TileCtx<T> ctx{P,
+                 cmem(reinterpret_cast<const float *>(d.params + param_offsets(N, M).f32)),
                  sx,
                  sup,
                  sdn,
@@ -924,20 +1030,26 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                  gmem(static_cast<const T *>(bufs.y)),
                  gmem(static_cast<T *>(bufs.out)),
                  sx0,
+                 sf0,
                  gmem(bufs.y0),
                  gmem(bufs.out0),
                  S,
                  i,
                  lane,
-                 damp,
+                 0.0,
                  coef};
-  tile_dispatch<N, KP, W, CH0, T, T, false>(wave, ctx);
-  const bool is0 = (i == 0);
   if constexpr (MIXED) {
-    // sigma_0 again, in FP64 from its FP64 copy; these writes follow the FP32
-    // ones above in program order, so they are the ones that remain.
-    if (is0) tile_dispatch<N, KP, W, CH0, double, T, true>(wave, ctx);
+    // sigma_0 in FP64: lane j of wave G takes packed element G + j W.
+    constexpr int P2 = N * (N + 1) / 2;
+    static_assert((P2 + W - 1) / W <= kTile, "sigma_0 elements of a wave exceed its lanes");
+    if (w.first == 0 && wave + lane * W < P2) tile_sigma0<N, KP, T>(ctx, wave + lane * W);
   }
+  if (!valid) return;  // no barrier below
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    ctx.damp = fmad(static_cast<double>(socc[m * kTile + lane]), P[2 * N * N + 4 * N + 2 * M + m],
+                    ctx.damp);
+  tile_dispatch<N, KP, W, CH0, T, T>(wave, ctx);
 }
 
 // ---------------------------------------------------------------------------
