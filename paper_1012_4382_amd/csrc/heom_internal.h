@@ -99,6 +99,7 @@ constexpr int kWideShape = 5;
 constexpr int kMaxTileShapes = kWideShape + 1;
 
 // A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
+// first = -1 marks the sigma_0 item of an FP32-mixed tile launch.
 struct WorkItem {
   int32_t inst;
   int32_t first;

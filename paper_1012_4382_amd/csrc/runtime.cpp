@@ -82,9 +82,9 @@ struct Layout {
 };
 
 // Work-list entries an instance of n_ados ADOs can need: its stage items in
-// 16-ADO and in 64-ADO tiles (a group may carry both lists), its
-// initialisation items (one per 64 ADOs) and the padding of each list to a
-// multiple of the XCD count.
+// 16-ADO and in 64-ADO tiles (a group may carry both lists), the sigma_0 item
+// of an FP32-mixed tile list, its initialisation items (one per 64 ADOs) and
+// the padding of each list to a multiple of the XCD count.
 int64_t work_items_cap(int64_t n_ados) {
   return (n_ados + 15) / 16 + 2 * ((n_ados + kPlanePad - 1) / kPlanePad) + 16;
 }
@@ -429,13 +429,17 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   }
   std::vector<WorkItem> items;
   std::vector<Group> groups;
-  // Appends the work list of `members` in items of `ados` ADOs, XCD-ordered.
-  auto add_list = [&](const std::vector<int> &members, int64_t ados, int64_t *begin,
+  // Appends the work list of `members` in items of `ados` ADOs, XCD-ordered;
+  // with `sigma0`, each instance's items are preceded by its sigma_0 item
+  // (first = -1, the FP64 update of sigma_0 in FP32-mixed tile launches).
+  auto add_list = [&](const std::vector<int> &members, int64_t ados, bool sigma0, int64_t *begin,
                       int64_t *count) {
     std::vector<WorkItem> mine;
-    for (int k : members)
+    for (int k : members) {
+      if (sigma0) mine.push_back({k, -1});
       for (int64_t first = 0; first < hs[k]->n_ados; first += ados)
         mine.push_back({k, static_cast<int32_t>(first)});
+    }
     if (xcd_remap()) {
       // Workgroup b runs on XCD b % kXcds.  Give XCD x the x-th contiguous
       // eighth of the list (consecutive tiles of the same instance), so that
@@ -467,16 +471,16 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
         tile = tile && shape_ok(hs[k], mixed, 0);
         wide = wide && shape_ok(hs[k], mixed, kWideShape);
       }
-      if (tile) add_list(kv.second, kPlanePad, &g.begin[0], &g.count[0]);
+      if (tile) add_list(kv.second, kPlanePad, mixed, &g.begin[0], &g.count[0]);
       if (wide) {
-        add_list(kv.second, 16, &g.begin[1], &g.count[1]);
+        add_list(kv.second, 16, false, &g.begin[1], &g.count[1]);
         HEOM_HIP(prepare_wide(g.N, g.N * g.KP, mixed), "wide kernel attributes");
       }
       g.shape = tile ? 0 : kWideShape;
       tile_shape_info(g.N, g.KP, mixed, g.shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
     } else {
       g.threads = block_ados();
-      add_list(kv.second, g.threads, &g.begin[0], &g.count[0]);
+      add_list(kv.second, g.threads, false, &g.begin[0], &g.count[0]);
     }
     groups.push_back(g);
   }

@@ -942,8 +942,8 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   constexpr int CH0 = tile_shape(sizeof(T) == 8, SHAPE).chunk;
   constexpr bool MIXED = sizeof(T) == 4;
   __shared__ T sx[(N2 + 1) * kTile];
-  __shared__ double sx0[MIXED ? N2 : 1];  // FP64 sigma_0 stage input, tile of ADO 0 only
-  __shared__ double sf0[MIXED ? 3 * N2 : 1];  // its unpacked form and H_re, tile of ADO 0
+  __shared__ double sx0[MIXED ? N2 : 1];      // FP64 sigma_0 stage input (sigma_0 item)
+  __shared__ double sf0[MIXED ? 3 * N2 : 1];  // its unpacked form and H_re (sigma_0 item)
   __shared__ int32_t sup[M * kTile];
   __shared__ int32_t sdn[M * kTile];
   __shared__ uint8_t socc[M * kTile];
@@ -954,12 +954,56 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   const int64_t S = d.stride;
   const int lane = threadIdx.x & (kTile - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t i = static_cast<int64_t>(w.first) + lane;
-  const bool valid = i < d.n_ados;
   const HEOM_GLOBAL T *X = gmem(static_cast<const T *>(bufs.x));
   const HEOM_GLOBAL int32_t *up = gmem(d.up);
   const HEOM_GLOBAL int32_t *dn = gmem(d.down);
   const HEOM_GLOBAL uint8_t *oc = gmem(d.occ);
+  if constexpr (MIXED) {
+    // The FP32-mixed work list carries one extra item per instance (first =
+    // -1): the FP64 update of sigma_0 and of the sink scalars, in a
+    // workgroup of its own, beside the tiles rather than after the tile of
+    // ADO 0.  The tile of ADO 0 leaves sigma_0 to it.
+    if (w.first < 0) {
+      for (int e = threadIdx.x; e < N2; e += blockDim.x) {
+        const int r = e / N, q = e % N;
+        const double re = bufs.x0[ent_re(N, r, q)];
+        const double im = r == q ? 0.0 : bufs.x0[ent_im(N, r, q)];
+        sx0[e] = bufs.x0[e];
+        sf0[e] = re;
+        sf0[N2 + e] = static_cast<double>(ent_sg(r, q)) * im;
+        sf0[2 * N2 + e] = d.params[e];
+      }
+      for (int m = threadIdx.x; m < M; m += blockDim.x) {  // ADO 0's table entries
+        sup[m * kTile] = up[m * S];
+        sdn[m * kTile] = dn[m * S];
+        socc[m * kTile] = oc[m * S];
+      }
+      __syncthreads();
+      if (wave == 0) scalar_update_wave(d, bufs, N, coef, lane, [&](int q) { return sx0[q]; });
+      const TileCtx<T> c0{cmem(d.params),
+                          cmem(reinterpret_cast<const float *>(d.params + param_offsets(N, M).f32)),
+                          sx,
+                          sup,
+                          sdn,
+                          socc,
+                          X,
+                          gmem(static_cast<const T *>(bufs.y)),
+                          gmem(static_cast<T *>(bufs.out)),
+                          sx0,
+                          sf0,
+                          gmem(bufs.y0),
+                          gmem(bufs.out0),
+                          S,
+                          0,
+                          lane,
+                          0.0,
+                          coef};
+      for (int p = threadIdx.x; p < N * (N + 1) / 2; p += blockDim.x) tile_sigma0<N, KP, T>(c0, p);
+      return;
+    }
+  }
+  const int64_t i = static_cast<int64_t>(w.first) + lane;
+  const bool valid = i < d.n_ados;
   // Stage the tile: wave w loads planes w, w + W, ... (a compile-time count,
   // clamped in bounds, so that every load is issued before the first wait).
   const int64_t ic = valid ? i : 0;  // invalid lanes load ADO 0 and store defaults
@@ -987,18 +1031,6 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
     if (e < N2) sx[e * kTile + lane] = valid ? vx[r] : T(0);
   }
   if (wave == 0) sx[N2 * kTile + lane] = T(0);
-  if constexpr (MIXED) {
-    if (w.first == 0)
-      for (int e = threadIdx.x; e < N2; e += blockDim.x) {
-        const int r = e / N, q = e % N;
-        const double re = bufs.x0[ent_re(N, r, q)];
-        const double im = r == q ? 0.0 : bufs.x0[ent_im(N, r, q)];
-        sx0[e] = bufs.x0[e];
-        sf0[e] = re;
-        sf0[N2 + e] = static_cast<double>(ent_sg(r, q)) * im;
-        sf0[2 * N2 + e] = d.params[e];
-      }
-  }
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
     const int m = wave + r * W;
@@ -1009,15 +1041,12 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
     }
   }
   __syncthreads();
-  // Sink fluxes and scalars of sigma_0: wave 0 of the first tile, every lane
-  // still active.
-  if (w.first == 0 && wave == 0) {
-    scalar_update_wave(d, bufs, N, coef, lane, [&](int s) {
-      if constexpr (MIXED)
-        return sx0[s];
-      else
-        return static_cast<double>(sx[s * kTile]);
-    });
+  // Sink fluxes and scalars of sigma_0 (FP64 storage; FP32-mixed runs do
+  // this in the sigma_0 item): wave 0 of the first tile, every lane still
+  // active.
+  if constexpr (!MIXED) {
+    if (w.first == 0 && wave == 0)
+      scalar_update_wave(d, bufs, N, coef, lane, [&](int q) { return sx[q * kTile]; });
   }
   const HEOM_CONST double *P = cmem(d.params);
   TileCtx<T> ctx{P,
@@ -1038,12 +1067,6 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                  lane,
                  0.0,
                  coef};
-  if constexpr (MIXED) {
-    // sigma_0 in FP64: lane j of wave G takes packed element G + j W.
-    constexpr int P2 = N * (N + 1) / 2;
-    static_assert((P2 + W - 1) / W <= kTile, "sigma_0 elements of a wave exceed its lanes");
-    if (w.first == 0 && wave + lane * W < P2) tile_sigma0<N, KP, T>(ctx, wave + lane * W);
-  }
   if (!valid) return;  // no barrier below
 #pragma unroll
   for (int m = 0; m < M; ++m)

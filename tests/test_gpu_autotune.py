@@ -52,11 +52,15 @@ def _cases():
         "chain8_d3": (_chain8(5), 3, workloads.site_state(8, 1)),
         "three_site_d5": (workloads.system(fmo["system"]["H"][:3, :3]), 5,
                           workloads.site_state(3, 1)),
+        # Fewer ADOs than the lanes that compute sigma_0 in FP32-mixed runs.
+        "fmo7_d1": (fmo["system"], 1, fmo["rho0"]),
+        "fmo7_d0": (fmo["system"], 0, fmo["rho0"]),
     }
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["fmo7_d4", "sweep7_k1_d3", "chain8_d3", "three_site_d5"])
+@pytest.mark.parametrize("case", ["fmo7_d4", "sweep7_k1_d3", "chain8_d3", "three_site_d5",
+                                  "fmo7_d1", "fmo7_d0"])
 def test_shapes_are_bitwise_identical(case, precision):
     sys_, depth, rho0 = _cases()[case]
     h = heom.Hierarchy(sys_, depth)
@@ -77,6 +81,26 @@ def test_shapes_are_bitwise_identical(case, precision):
         assert np.array_equal(rho, ref[0]), s
         assert np.array_equal(sinks, ref[1]), s
         assert np.array_equal(state, ref[2]), s
+
+
+@pytest.mark.parametrize("n_sites,depth", [(7, 0), (7, 1), (2, 1), (12, 1)])
+def test_fp32_sigma0_on_tiny_hierarchies(n_sites, depth):
+    """FP32-mixed runs compute sigma_0 in FP64 with one lane per packed
+    element, also where those lanes lie past the last ADO of the tile."""
+    rng = np.random.default_rng(40 + n_sites)
+    H = workloads.fmo_like_hamiltonian(rng, n_sites)
+    trap, rec = workloads.fmo_sinks(n_sites, trap_site=min(3, n_sites))
+    sys_ = workloads.system(H, trap=trap, rec=rec)
+    rho0 = workloads.site_state(n_sites, 1)
+    _say(f"case: fp32 sigma_0, N={n_sites} depth={depth}")
+    h = heom.Hierarchy(sys_, depth)
+    rho, sinks, _ = heom.propagate(h, rho0, 1.0, 300, record_every=10, precision="fp32")
+    ref = oracle.propagate(sys_, depth, rho0, 1.0, 300, record_every=10)
+    p = np.real(np.diagonal(rho, axis1=1, axis2=2))
+    pr = np.real(np.diagonal(ref["rho"], axis1=1, axis2=2))
+    assert np.max(np.abs(p - pr)) <= 1e-5
+    assert np.max(np.abs(rho - ref["rho"])) <= 1e-5
+    assert abs(sinks[0] - ref["scalars"][0]) <= 1e-5
 
 
 def test_forced_shape_matches_oracle():
