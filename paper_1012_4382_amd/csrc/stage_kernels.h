@@ -35,7 +35,9 @@
 // ADOs is a contiguous segment, and neighbour gathers (whose indices are
 // nearly consecutive in the lexicographic order of the hierarchy) touch few
 // cache lines.  The sigma_0 part of each stage (sink fluxes, P_trap, P_rec, Q)
-// is done where ADO 0 is; history records are written by the snapshot kernel.
+// is done where ADO 0 is (in FP32-mixed tile launches, by a work item of its
+// own that also updates sigma_0 in FP64); history records are written by the
+// snapshot kernel.
 //
 // Kernels:
 //  * stage_tile<N, KP, T, shape> (N <= 12, real H): 64-ADO tiles in LDS,
@@ -652,7 +654,7 @@ struct TileCtx {
   HEOM_GLOBAL T *Out;                 // output planes
   const double *sx0;                  // LDS copy of the FP64 sigma_0 stage input (mixed)
   const double *sf0;                  // the same, unpacked: Re [N*N], Im [N*N], and H_re
-                                      // [N*N] (mixed, first tile only)
+                                      // [N*N] (mixed, sigma_0 item only)
   const HEOM_GLOBAL double *y0;       // FP64 sigma_0 state (mixed precision)
   HEOM_GLOBAL double *out0;           // FP64 sigma_0 output (mixed precision)
   int64_t S, i;
@@ -834,7 +836,8 @@ __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
 }
 
 // sigma_0 of an FP32-mixed run, in FP64 (packed element p, chosen at run
-// time, so that one lane per element covers sigma_0): the right-hand side
+// time, so that one lane per element of the sigma_0 work item covers
+// sigma_0): the right-hand side
 // from the FP64 copy of the stage input (LDS), the FP32 neighbour planes and
 // the FP64 state, with the operations of tile_finish in the same order, so
 // the result does not depend on the launch shape.  It is the only writer of
