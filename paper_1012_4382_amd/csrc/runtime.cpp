@@ -243,6 +243,45 @@ int capture_stream(int device, hipStream_t *out) {
   return HEOM_OK;
 }
 
+// Streams and events that let the kernel groups of one RK4 stage run side by
+// side: each group's launch touches only its own instances, so only the
+// stages must follow each other.  One set per device and host thread, kept
+// for the life of the process; default priority.
+struct ForkJoin {
+  hipEvent_t fork = nullptr;
+  std::vector<hipStream_t> aux;  // aux[g], g >= 1: stream of group g
+  std::vector<hipEvent_t> join;  // join[g]: group g's launch is done
+};
+
+int fork_join(int device, size_t n_groups, ForkJoin **out) {
+  thread_local std::map<int, ForkJoin> sets;
+  ForkJoin &f = sets[device];
+  if (!f.fork) {
+    hipError_t e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      f.fork = nullptr;
+      return dev_fail(e, "hipEventCreateWithFlags");
+    }
+    f.aux.push_back(nullptr);  // group 0 runs on the caller's stream
+    f.join.push_back(nullptr);
+  }
+  while (f.aux.size() < n_groups) {
+    hipStream_t st;
+    hipEvent_t ev;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return dev_fail(e, "hipStreamCreateWithFlags");
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(st);
+      return dev_fail(e, "hipEventCreateWithFlags");
+    }
+    f.aux.push_back(st);
+    f.join.push_back(ev);
+  }
+  *out = &f;
+  return HEOM_OK;
+}
+
 // A graph of k RK4 steps, destroyed with the object.
 struct StepGraph {
   hipGraph_t graph = nullptr;
@@ -612,16 +651,40 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     g.shape = shape;
     tile_shape_info(g.N, g.KP, mixed, shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
   }
-  // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.
+  // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.  With
+  // several groups, each stage forks: group 0 runs on `s`, group g on its own
+  // stream, and `s` waits for all of them before the next stage.  (In a
+  // graph capture this gives parallel branches.)
+  ForkJoin *fj = nullptr;
+  if (groups.size() > 1) {
+    int rc = fork_join(device, groups.size(), &fj);
+    if (rc) return rc;
+  }
+  auto launch_group = [&](const Group &g, int st, hipStream_t s) -> hipError_t {
+    const int l = g.list(g.shape);
+    return launch_stage(g.kind, mixed, g.N, g.KP, g.shape, d_descs, d_work + g.begin[l],
+                        static_cast<int>(g.count[l]), g.threads, st, coef[st], -1, s);
+  };
   auto enqueue_step = [&](hipStream_t s) -> hipError_t {
-    for (int st = 0; st < 4; ++st)
-      for (const Group &g : groups) {
-        const int l = g.list(g.shape);
-        hipError_t e = launch_stage(g.kind, mixed, g.N, g.KP, g.shape, d_descs,
-                                    d_work + g.begin[l], static_cast<int>(g.count[l]), g.threads,
-                                    st, coef[st], -1, s);
+    for (int st = 0; st < 4; ++st) {
+      hipError_t e = hipSuccess;
+      if (!fj) {
+        for (const Group &g : groups)
+          if (e == hipSuccess) e = launch_group(g, st, s);
         if (e != hipSuccess) return e;
+        continue;
       }
+      e = hipEventRecord(fj->fork, s);
+      for (size_t gi = 1; gi < groups.size() && e == hipSuccess; ++gi) {
+        e = hipStreamWaitEvent(fj->aux[gi], fj->fork, 0);
+        if (e == hipSuccess) e = launch_group(groups[gi], st, fj->aux[gi]);
+        if (e == hipSuccess) e = hipEventRecord(fj->join[gi], fj->aux[gi]);
+      }
+      if (e == hipSuccess) e = launch_group(groups[0], st, s);
+      for (size_t gi = 1; gi < groups.size() && e == hipSuccess; ++gi)
+        e = hipStreamWaitEvent(s, fj->join[gi], 0);
+      if (e != hipSuccess) return e;
+    }
     return hipSuccess;
   };
   // Runs of kGraphSteps steps are replayed from one captured graph, which
