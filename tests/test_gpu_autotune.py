@@ -103,6 +103,35 @@ def test_fp32_sigma0_on_tiny_hierarchies(n_sites, depth):
     assert abs(sinks[0] - ref["scalars"][0]) <= 1e-5
 
 
+@pytest.mark.parametrize("n_sites", [9, 10, 11, 12])
+@pytest.mark.parametrize("shape", [0, 5])
+def test_tile_and_wide_shapes_for_9_to_12_sites(n_sites, shape):
+    """N = 9-12: the tile kernel (shape 0, the only tile shape built for them,
+    with its sigma_0 work item in FP32-mixed runs) and the wide kernel
+    (shape 5) against the oracle, and bitwise equal to each other."""
+    rng = np.random.default_rng(60 + n_sites)
+    H = workloads.fmo_like_hamiltonian(rng, n_sites)
+    trap, rec = workloads.fmo_sinks(n_sites, trap_site=3)
+    sys_ = workloads.system(H, trap=trap, rec=rec)
+    rho0 = workloads.site_state(n_sites, 1)
+    ref = oracle.propagate(sys_, 2, rho0, 1.0, 150, record_every=10)
+    h = heom.Hierarchy(sys_, 2)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _say(f"case: N={n_sites} depth 2 {prec} shape {shape}")
+        rho, sinks, _ = heom.propagate(h, rho0, 1.0, 150, record_every=10, precision=prec,
+                                       tile_shape=shape)
+        other, osinks, _ = heom.propagate(h, rho0, 1.0, 150, record_every=10, precision=prec,
+                                          tile_shape=5 - shape)
+        assert np.array_equal(rho, other) and np.array_equal(sinks, osinks)
+        if prec == "fp64":
+            assert float(np.max(np.abs(rho - ref["rho"])) / np.max(np.abs(ref["rho"]))) <= 1e-10
+            assert abs(sinks[0] - ref["scalars"][0]) <= 1e-10 * max(abs(ref["scalars"][0]), 1e-3)
+        else:
+            assert np.max(np.abs(rho - ref["rho"])) <= 1e-5
+            assert abs(sinks[0] - ref["scalars"][0]) <= 1e-5
+
+
 def test_forced_shape_matches_oracle():
     w = workloads.fmo_like(seed=0, site=6, depth=3, steps=300)
     h = heom.Hierarchy(w["system"], w["depth"])
