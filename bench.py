@@ -403,8 +403,10 @@ def main():
         "autotune": autotune,
     }
     if not args.no_variants:
-        # Plain single solve (one instance at a time) and FP32-mixed batch.
+        # Plain single solve (one instance at a time, FP64 and FP32-mixed, each
+        # after a short warm-up call) and the FP32-mixed batch.
         ws1 = heom.allocate_workspace(hs[0].workspace_bytes[heom.HEOM_FP64])
+        heom.propagate(hs[0], rho0s[0], 1.0, 64, record_every=64, workspace=ws1, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         heom.propagate(hs[0], rho0s[0], 1.0, steps_rk, record_every=record_every, workspace=ws1,
@@ -418,7 +420,18 @@ def main():
         one_pass("fp32", ws32)
         torch.cuda.synchronize()
         fp32 = total_ados * steps_rk / (time.perf_counter() - t0)
+        ws1f = heom.allocate_workspace(hs[0].workspace_bytes[heom.HEOM_FP32_MIXED])
+        heom.propagate(hs[0], rho0s[0], 1.0, 64, record_every=64, workspace=ws1f, stream=stream,
+                       precision="fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        heom.propagate(hs[0], rho0s[0], 1.0, steps_rk, record_every=record_every, workspace=ws1f,
+                       stream=stream, precision="fp32")
+        torch.cuda.synchronize()
+        plain32 = n_ados * steps_rk / (time.perf_counter() - t0)
         result["variants"] = {"fp64_single_solve_ado_steps_per_s": plain,
+                              "fp32_single_solve_ado_steps_per_s": plain32,
+                              "fp32_batched_over_single": fp32 / plain32,
                               "fp32_mixed_batched_ado_steps_per_s": fp32,
                               "fp64_batched_over_single": value / plain}
     if not args.no_sizing:
