@@ -198,6 +198,23 @@ def test_fp32_mixed_against_fp64_oracle(T, kernel):
     assert err_eta <= FP32_TOL * max(1.0, ref["scalars"][0])
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32_mixed_matsubara_sweep_shape(kernel):
+    """FP32-mixed with one Matsubara term per bath (14 modes, the sweep's
+    shape), depth 3, 1000 steps, against the FP64 oracle."""
+    w = workloads.sweep_instance(0)
+    w["depth"] = 3
+    _say(f"case: fp32-mixed sweep instance 0, N=7 K=1 D=3, 1000 steps kernel={kernel}")
+    h = heom.Hierarchy(w["system"], w["depth"])
+    rho, sinks, _ = heom.propagate(h, w["rho0"], w["dt"], w["steps"], record_every=5,
+                                   precision="fp32", kernel=kernel)
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"], record_every=5)
+    p = np.real(np.diagonal(rho, axis1=1, axis2=2))
+    pr = np.real(np.diagonal(ref["rho"], axis1=1, axis2=2))
+    assert np.max(np.abs(p - pr)) <= FP32_TOL
+    assert abs(sinks[0] - ref["scalars"][0]) <= FP32_TOL * max(1.0, ref["scalars"][0])
+
+
 def test_fp32_mixed_full_size_sampled():
     """Precision workload shape (depth 8, 6435 ADOs): first 100 steps vs oracle."""
     w = workloads.fmo_like(seed=1, site=1, depth=8, T=77.0, steps=100)
