@@ -7,9 +7,13 @@ site 1 or site 6), each propagated 5000 RK4 steps of 1 fs (5 ps) in FP64 with
 trapping and recombination sinks, as one batched launch sequence.  Inputs,
 tables and parameters are on the device before the timed region starts.
 
-Printed: one JSON line with ADO-steps/s (whole job), the single-solve and
-FP32-mixed rates, the roofline of the dominant kernel, and the oracle timed on
-this host on a bounded sample.
+Printed: one JSON line with ADO-steps/s (whole job), the roofline of the
+dominant kernel (on the classic RK4 algorithmic bytes and on the bytes the
+nested form moves, with the counted traffic of the committed profile), and the
+oracle timed on this host on a bounded sample.  Further legs, each skippable:
+single-solve and FP32-mixed rates, the depth-16 and 24-site sizing launches,
+batch scaling (2-128 solves, and a plain device copy for scale), the
+64-instance parameter sweep, the precision comparison, and serving.
 """
 from __future__ import annotations
 
