@@ -6,41 +6,66 @@
 namespace heom {
 
 typedef StageKernel (*TilePart)(int N, int KP, bool mixed);
-// Tile instances by shape: N <= 8 in every shape, N = 9..12 in shape 0 only.
-StageKernel tile_kernel_part_small_s0(int, int, bool);
-StageKernel tile_kernel_part_small_s1(int, int, bool);
-StageKernel tile_kernel_part_small_s2(int, int, bool);
-StageKernel tile_kernel_part_7_s0(int, int, bool);
-StageKernel tile_kernel_part_7_s1(int, int, bool);
-StageKernel tile_kernel_part_7_s2(int, int, bool);
-StageKernel tile_kernel_part_8_s0(int, int, bool);
-StageKernel tile_kernel_part_8_s1(int, int, bool);
-StageKernel tile_kernel_part_8_s2(int, int, bool);
-StageKernel tile_kernel_part_small_s3(int, int, bool);
-StageKernel tile_kernel_part_7_s3(int, int, bool);
-StageKernel tile_kernel_part_8_s3(int, int, bool);
-StageKernel tile_kernel_part_small_s4(int, int, bool);
-StageKernel tile_kernel_part_7_s4(int, int, bool);
-StageKernel tile_kernel_part_8_s4(int, int, bool);
-StageKernel tile_kernel_part_9_10_s0(int, int, bool);
-StageKernel tile_kernel_part_11_s0(int, int, bool);
-StageKernel tile_kernel_part_12_s0(int, int, bool);
+// Tile instances by shape and storage precision (_f1: FP64, _f0: FP32-mixed):
+// N <= 8 in every shape, N = 9..12 in shape 0 only.
+StageKernel tile_kernel_part_small_s0_f1(int, int, bool);
+StageKernel tile_kernel_part_small_s0_f0(int, int, bool);
+StageKernel tile_kernel_part_7_s0_f1(int, int, bool);
+StageKernel tile_kernel_part_7_s0_f0(int, int, bool);
+StageKernel tile_kernel_part_8_s0_f1(int, int, bool);
+StageKernel tile_kernel_part_8_s0_f0(int, int, bool);
+StageKernel tile_kernel_part_9_10_s0_f1(int, int, bool);
+StageKernel tile_kernel_part_9_10_s0_f0(int, int, bool);
+StageKernel tile_kernel_part_11_s0_f1(int, int, bool);
+StageKernel tile_kernel_part_11_s0_f0(int, int, bool);
+StageKernel tile_kernel_part_12_s0_f1(int, int, bool);
+StageKernel tile_kernel_part_12_s0_f0(int, int, bool);
+StageKernel tile_kernel_part_small_s1_f1(int, int, bool);
+StageKernel tile_kernel_part_small_s1_f0(int, int, bool);
+StageKernel tile_kernel_part_7_s1_f1(int, int, bool);
+StageKernel tile_kernel_part_7_s1_f0(int, int, bool);
+StageKernel tile_kernel_part_8_s1_f1(int, int, bool);
+StageKernel tile_kernel_part_8_s1_f0(int, int, bool);
+StageKernel tile_kernel_part_small_s2_f1(int, int, bool);
+StageKernel tile_kernel_part_small_s2_f0(int, int, bool);
+StageKernel tile_kernel_part_7_s2_f1(int, int, bool);
+StageKernel tile_kernel_part_7_s2_f0(int, int, bool);
+StageKernel tile_kernel_part_8_s2_f1(int, int, bool);
+StageKernel tile_kernel_part_8_s2_f0(int, int, bool);
+StageKernel tile_kernel_part_small_s3_f1(int, int, bool);
+StageKernel tile_kernel_part_small_s3_f0(int, int, bool);
+StageKernel tile_kernel_part_7_s3_f1(int, int, bool);
+StageKernel tile_kernel_part_7_s3_f0(int, int, bool);
+StageKernel tile_kernel_part_8_s3_f1(int, int, bool);
+StageKernel tile_kernel_part_8_s3_f0(int, int, bool);
+StageKernel tile_kernel_part_small_s4_f1(int, int, bool);
+StageKernel tile_kernel_part_small_s4_f0(int, int, bool);
+StageKernel tile_kernel_part_7_s4_f1(int, int, bool);
+StageKernel tile_kernel_part_7_s4_f0(int, int, bool);
+StageKernel tile_kernel_part_8_s4_f1(int, int, bool);
+StageKernel tile_kernel_part_8_s4_f0(int, int, bool);
 StageKernel lane_kernel_ptr(int N, int KP, bool mixed);
 
 namespace {
 
 static_assert(kTileShapes == 5, "one row of tile parts per shape");
-constexpr TilePart kTileParts[kTileShapes][6] = {
-    {&tile_kernel_part_small_s0, &tile_kernel_part_7_s0, &tile_kernel_part_8_s0,
-     &tile_kernel_part_9_10_s0, &tile_kernel_part_11_s0, &tile_kernel_part_12_s0},
-    {&tile_kernel_part_small_s1, &tile_kernel_part_7_s1, &tile_kernel_part_8_s1, nullptr, nullptr,
-     nullptr},
-    {&tile_kernel_part_small_s2, &tile_kernel_part_7_s2, &tile_kernel_part_8_s2, nullptr, nullptr,
-     nullptr},
-    {&tile_kernel_part_small_s3, &tile_kernel_part_7_s3, &tile_kernel_part_8_s3, nullptr, nullptr,
-     nullptr},
-    {&tile_kernel_part_small_s4, &tile_kernel_part_7_s4, &tile_kernel_part_8_s4, nullptr, nullptr,
-     nullptr},
+constexpr TilePart kTileParts[kTileShapes][12] = {
+    {&tile_kernel_part_small_s0_f1, &tile_kernel_part_small_s0_f0, &tile_kernel_part_7_s0_f1,
+     &tile_kernel_part_7_s0_f0, &tile_kernel_part_8_s0_f1, &tile_kernel_part_8_s0_f0,
+     &tile_kernel_part_9_10_s0_f1, &tile_kernel_part_9_10_s0_f0, &tile_kernel_part_11_s0_f1,
+     &tile_kernel_part_11_s0_f0, &tile_kernel_part_12_s0_f1, &tile_kernel_part_12_s0_f0},
+    {&tile_kernel_part_small_s1_f1, &tile_kernel_part_small_s1_f0, &tile_kernel_part_7_s1_f1,
+     &tile_kernel_part_7_s1_f0, &tile_kernel_part_8_s1_f1, &tile_kernel_part_8_s1_f0, nullptr,
+     nullptr, nullptr, nullptr, nullptr, nullptr},
+    {&tile_kernel_part_small_s2_f1, &tile_kernel_part_small_s2_f0, &tile_kernel_part_7_s2_f1,
+     &tile_kernel_part_7_s2_f0, &tile_kernel_part_8_s2_f1, &tile_kernel_part_8_s2_f0, nullptr,
+     nullptr, nullptr, nullptr, nullptr, nullptr},
+    {&tile_kernel_part_small_s3_f1, &tile_kernel_part_small_s3_f0, &tile_kernel_part_7_s3_f1,
+     &tile_kernel_part_7_s3_f0, &tile_kernel_part_8_s3_f1, &tile_kernel_part_8_s3_f0, nullptr,
+     nullptr, nullptr, nullptr, nullptr, nullptr},
+    {&tile_kernel_part_small_s4_f1, &tile_kernel_part_small_s4_f0, &tile_kernel_part_7_s4_f1,
+     &tile_kernel_part_7_s4_f0, &tile_kernel_part_8_s4_f1, &tile_kernel_part_8_s4_f0, nullptr,
+     nullptr, nullptr, nullptr, nullptr, nullptr},
 };
 
 StageKernel tile_kernel(int N, int KP, bool mixed, int shape) {

@@ -1,7 +1,8 @@
 // kernels_tile_9_10.hip -- instances of the tile stage kernel for
 // N=9 K+1=1, N=10 K+1=1
-// (FP64 and FP32-mixed storage) in launch shape HEOM_SHAPE: the unit is
-// compiled once per shape it provides.
+// in launch shape HEOM_SHAPE and storage precision HEOM_TILE_F64 (FP64 or
+// FP32-mixed): the unit is compiled once per shape it provides and per
+// precision.
 #include "stage_kernels.h"
 
 namespace heom {
@@ -9,9 +10,9 @@ namespace heom {
 StageKernel HEOM_SHAPED(tile_kernel_part_9_10)(int N, int KP, bool mixed) {
   constexpr int S = HEOM_SHAPE;
   if (N == 9 && KP == 1)
-    return mixed ? &stage_tile<9, 1, float, S> : &stage_tile<9, 1, double, S>;
+    return tile_instance<9, 1, S>(mixed);
   if (N == 10 && KP == 1)
-    return mixed ? &stage_tile<10, 1, float, S> : &stage_tile<10, 1, double, S>;
+    return tile_instance<10, 1, S>(mixed);
   return nullptr;
 }
 

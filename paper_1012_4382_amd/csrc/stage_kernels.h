@@ -633,14 +633,19 @@ __host__ __device__ constexpr int tile_waves(int N, bool fp64, int s) {
   return tile_waves_for(N, tile_shape(fp64, s).elems_per_wave);
 }
 
-// The tile units are compiled once per shape (HEOM_SHAPE); their instance
-// tables carry the shape in their names.
+// The tile units are compiled once per shape (HEOM_SHAPE) and storage
+// precision (HEOM_TILE_F64: 1 for the FP64 instances, 0 for the FP32-mixed
+// ones, so that each precision can be built with its own code-generation
+// options); their instance tables carry both in their names.
 #ifndef HEOM_SHAPE
 #define HEOM_SHAPE 0
 #endif
-#define HEOM_SHAPED_CAT(name, s) name##_s##s
-#define HEOM_SHAPED_EXPAND(name, s) HEOM_SHAPED_CAT(name, s)
-#define HEOM_SHAPED(name) HEOM_SHAPED_EXPAND(name, HEOM_SHAPE)
+#ifndef HEOM_TILE_F64
+#define HEOM_TILE_F64 1
+#endif
+#define HEOM_SHAPED_CAT(name, s, f) name##_s##s##_f##f
+#define HEOM_SHAPED_EXPAND(name, s, f) HEOM_SHAPED_CAT(name, s, f)
+#define HEOM_SHAPED(name) HEOM_SHAPED_EXPAND(name, HEOM_SHAPE, HEOM_TILE_F64)
 
 template <typename T>
 struct TileCtx {
@@ -1076,6 +1081,17 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
     ctx.damp = fmad(static_cast<double>(socc[m * kTile + lane]), P[2 * N * N + 4 * N + 2 * M + m],
                     ctx.damp);
   tile_dispatch<N, KP, W, CH0, T, T>(wave, ctx);
+}
+
+// The instance of a tile unit for storage `mixed`: null for the precision the
+// unit is not compiled for (the other unit of the same shape provides it).
+template <int N, int KP, int S>
+StageKernel tile_instance(bool mixed) {
+#if HEOM_TILE_F64
+  return mixed ? nullptr : &stage_tile<N, KP, double, S>;
+#else
+  return mixed ? &stage_tile<N, KP, float, S> : nullptr;
+#endif
 }
 
 // ---------------------------------------------------------------------------
