@@ -174,8 +174,8 @@ def test_product_path_does_not_use_the_oracle():
 
 def test_tile_shapes_and_forced_shape_validation():
     """Launch shapes: the 64-ADO tile kernel in shapes 0-4 (every N <= 12 has
-    shape 0, N <= 8 all five), its waves dividing the N(N+1)/2 packed
-    elements; the 16-ADO wide kernel as shape 5 for N <= 32; a forced shape
+    shape 0, N <= 8 all five, with one Matsubara term N <= 8), its waves
+    dividing the N(N+1)/2 packed elements; the 16-ADO wide kernel as shape 5 for N <= 32; a forced shape
     that is out of range or not built is rejected before device work."""
     lib = heom.library()
     count = heom.tile_shape_count()
@@ -185,13 +185,16 @@ def test_tile_shapes_and_forced_shape_validation():
         P = N * (N + 1) // 2
         for prec in ("fp64", "fp32"):
             for s in range(wide):
-                info = heom.tile_shape_info(N, 1, prec, s)
-                assert (info is not None) == (N <= 8 or (s == 0 and N <= 12)), (N, prec, s)
-                if info is not None:
-                    ados, threads, epw, chunk, waves = info
-                    assert ados == 64 and threads % 64 == 0 and 64 <= threads <= 1024
-                    assert P % (threads // 64) == 0 and epw >= 1 and chunk >= 1
-                    assert 1 <= waves <= 8
+                # K + 1 = 1: N <= 8 in every shape, N <= 12 in shape 0;
+                # K + 1 = 2: N <= 8 in every shape.  Both storage types.
+                for kp, built in ((1, N <= 8 or (s == 0 and N <= 12)), (2, N <= 8)):
+                    info = heom.tile_shape_info(N, kp, prec, s)
+                    assert (info is not None) == built, (N, kp, prec, s)
+                    if info is not None:
+                        ados, threads, epw, chunk, waves = info
+                        assert ados == 64 and threads % 64 == 0 and 64 <= threads <= 1024
+                        assert P % (threads // 64) == 0 and epw >= 1 and chunk >= 1
+                        assert 1 <= waves <= 8
             for kp in (1, 2, 4):
                 info = heom.tile_shape_info(N, kp, prec, wide)
                 # LDS bound: with 4 modes per site, FP64 tiles of 32 sites do not fit.
