@@ -371,12 +371,14 @@ def main():
     moved = bytes_moved / (kernel_ms * 1e-3) / 1e9
     # Launch shape the autotuner chose for this workload (during the warm-up).
     n_tiles = sum((h.n_ados + 63) // 64 for h in hs)
-    shape, shape_us = heom.autotune_lookup(N, 1, n_tiles, "fp64")
-    kernel_name = {"auto": f"stage_tile<{N},1,double,{max(shape, 0)}>",
+    shape, shape_us, streaming, streaming_us = heom.autotune_lookup(N, 1, n_tiles, "fp64")
+    kernel_name = {"auto": f"stage_tile<{N},1,double,{max(shape, 0)}>"
+                           + (" with streaming stores" if streaming == 1 else ""),
                    "lane": f"stage_fixed<{N},1,double>",
                    "generic": "stage_generic<double>"}[args.kernel]
-    autotune = {"tiles": n_tiles, "shape": shape,
+    autotune = {"tiles": n_tiles, "shape": shape, "streaming_stores": streaming,
                 "stage_us_per_shape": [round(float(u), 3) for u in shape_us],
+                "stage_us_streaming": round(float(streaming_us), 3),
                 "shapes": [heom.tile_shape_info(N, 1, "fp64", k)
                            for k in range(heom.tile_shape_count())]}
 

@@ -63,8 +63,15 @@ enum {
                                kernel instead of the LDS-tiled one (N <= 8)     */
   HEOM_NO_GRAPH = 8,        /* diagnostic: launch every stage kernel directly
                                instead of replaying captured graphs of steps    */
-  HEOM_NO_AUTOTUNE = 16     /* use the default launch shape of the LDS-tiled
+  HEOM_NO_AUTOTUNE = 16,    /* use the default launch shape of the LDS-tiled
                                kernels instead of the autotuned one             */
+  HEOM_STREAMING_STORES = 32, /* FP64 tile kernels write their output with
+                               non-temporal (streaming) stores (other kernels
+                               always store plainly)                            */
+  HEOM_PLAIN_STORES = 64    /* tile kernels write their output with plain
+                               stores (exclusive with HEOM_STREAMING_STORES;
+                               without either, the autotuner's policy, or
+                               plain stores where no tuning is done)            */
 };
 /* Flag bits that force tile launch shape s (0 <= s < heom_tile_shape_count())
  * for every tile-kernel group of a call. */
@@ -136,7 +143,8 @@ int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, d
  *   flags          HEOM_RESUME: continue the run held in d_workspace (rho0 is
  *                  then ignored and may be NULL); HEOM_GENERIC_KERNEL,
  *                  HEOM_LANE_KERNEL, HEOM_NO_GRAPH, HEOM_NO_AUTOTUNE,
- *                  HEOM_TILE_SHAPE(s) (see the autotuner below)
+ *                  HEOM_STREAMING_STORES, HEOM_PLAIN_STORES, HEOM_TILE_SHAPE(s)
+ *                  (see the autotuner below)
  *   rho0           [N][N] complex Hermitian initial reduced density matrix;
  *                  every deeper ADO starts at zero (text after eq:lab8)
  *   record_every   >= 1; rho is recorded at step 0 and every record_every steps
@@ -181,7 +189,8 @@ int heom_slots_scratch_bytes(heom_hierarchy *const *hs, int32_t n, size_t *bytes
  *                       Hermitian); 0: continue the run held in its workspace
  *                       (as HEOM_RESUME; rho0s[i] may be NULL)
  *   flags               HEOM_GENERIC_KERNEL, HEOM_LANE_KERNEL, HEOM_NO_GRAPH,
- *                       HEOM_NO_AUTOTUNE, HEOM_TILE_SHAPE(s)
+ *                       HEOM_NO_AUTOTUNE, HEOM_STREAMING_STORES,
+ *                       HEOM_PLAIN_STORES, HEOM_TILE_SHAPE(s)
  *   d_scratch           at least heom_slots_scratch_bytes(hs, n) bytes, 256-byte
  *                       aligned; its contents are not needed after the call
  *   rho_out[i]          host N*N complex: sigma_0 after the last step, or NULL
@@ -230,8 +239,11 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
  * precision, N, K + 1, floor(log2(tiles))) - tiles being the 64-ADO blocks of
  * all of the call's instances with that N and K + 1 - times each distinct
  * available shape on its own launch (repeated sequences of RK4 stages 1, 2,
- * 3, 2, which never write the state, so the run is unchanged), then uses and
- * remembers the fastest; later calls with that key reuse it.  If the
+ * 3, 2, which never write the state, so the run is unchanged), then the
+ * fastest one again with non-temporal (streaming) output stores where that
+ * instance is built (FP64 tile shapes 0-4), and uses and remembers the faster
+ * configuration; later calls with that key reuse it.
+ * Results do not depend on the store policy either.  If the
  * environment variable HEOM_AUTOTUNE_CACHE names a file, entries are read
  * from it on first use and new ones are appended (one JSON object per line).
  *
@@ -242,8 +254,11 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
  *   be NULL.  HEOM_E_UNSUPPORTED if the shape is not built for this N.
  * heom_autotune_lookup: the tuned shape for that key on the current device,
  *   or -1 if not tuned yet; us_per_shape [count] (or NULL) receives the
- *   measured microseconds per stage launch of each shape, -1 where a shape
- *   was not timed.
+ *   measured microseconds per stage launch of each shape with plain stores,
+ *   -1 where a shape was not timed; streaming (or NULL) whether the tuned
+ *   configuration uses streaming stores (1, 0, or -1 if not tuned), and
+ *   us_streaming (or NULL) the tuned shape's time with them (-1 where that
+ *   instance is not built).
  * heom_autotune_clear: forgets every tuned entry of the process (entries in
  *   the cache file are read again on next use). */
 int heom_tile_shape_count(void);
@@ -251,7 +266,8 @@ int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision,
                          int32_t *ados_per_workgroup, int32_t *threads, int32_t *elems_per_wave,
                          int32_t *chunk, int32_t *min_waves_per_simd);
 int heom_autotune_lookup(int32_t n_sites, int32_t modes_per_site, int precision, int64_t n_tiles,
-                         int32_t *shape, double *us_per_shape);
+                         int32_t *shape, double *us_per_shape, int32_t *streaming,
+                         double *us_streaming);
 void heom_autotune_clear(void);
 
 /* Releases a handle and its device tables.  NULL is accepted. */

@@ -7,8 +7,9 @@
 // long load batches, a launch of thousands of tiles is bandwidth-bound and
 // prefers shapes that keep more workgroups resident.  The tuner keys its
 // choice on (GPU architecture, precision, N, K+1, floor(log2(tiles))), times
-// every candidate once per key on the caller's own launch (see run_impl), and
-// remembers the fastest for the life of the process.  If HEOM_AUTOTUNE_CACHE
+// every candidate once per key on the caller's own launch (see run_impl),
+// then the fastest one again with non-temporal (streaming) output stores, and
+// remembers the faster configuration for the life of the process.  If HEOM_AUTOTUNE_CACHE
 // names a file, its entries are read on first use and new entries are
 // appended to it, one JSON object per line.
 #include <hip/hip_runtime_api.h>
@@ -30,7 +31,9 @@ namespace {
 
 struct Entry {
   int shape = -1;
-  double us[kMaxTileShapes];
+  int streaming = 0;          // non-temporal output stores
+  double us[kMaxTileShapes];  // per shape, plain stores
+  double us_streaming = -1.0;  // the chosen shape with streaming stores
 };
 
 // (arch, mixed, N, K+1, floor(log2(tiles)))
@@ -73,15 +76,16 @@ std::string arch_of(int device) {
 
 // One line of the cache file (one timing per shape slot, -1 where untimed):
 // {"arch": "gfx950", "precision": 0, "N": 7, "KP": 1, "tiles_log2": 8, "shape": 1,
-//  "us": [10.6, 9.8, 12.0, -1.0, 11.1]}
+//  "streaming": 0, "us": [10.6, 9.8, 12.0, -1.0, 11.1, 30.2], "us_streaming": 10.1}
 bool parse_line(const char *line, Key *key, Entry *e) {
   char arch[64] = {0};
-  int prec, N, KP, tl, shape, used = 0;
+  int prec, N, KP, tl, shape, streaming, used = 0;
   const int got = std::sscanf(line,
                               " {\"arch\": \"%63[^\"]\", \"precision\": %d, \"N\": %d, \"KP\": %d, "
-                              "\"tiles_log2\": %d, \"shape\": %d, \"us\": [%n",
-                              arch, &prec, &N, &KP, &tl, &shape, &used);
-  if (got != 6 || used == 0 || shape < 0 || shape >= kMaxTileShapes) return false;
+                              "\"tiles_log2\": %d, \"shape\": %d, \"streaming\": %d, \"us\": [%n",
+                              arch, &prec, &N, &KP, &tl, &shape, &streaming, &used);
+  if (got != 7 || used == 0 || shape < 0 || shape >= kMaxTileShapes) return false;
+  if (streaming != 0 && streaming != 1) return false;
   const char *p = line + used;
   for (int s = 0; s < kMaxTileShapes; ++s) {
     char *end = nullptr;
@@ -91,7 +95,11 @@ bool parse_line(const char *line, Key *key, Entry *e) {
     while (*p == ',' || *p == ' ') ++p;
   }
   if (*p != ']') return false;
+  int tail = 0;
+  if (std::sscanf(p, "], \"us_streaming\": %lf}%n", &e->us_streaming, &tail) != 1 || tail == 0)
+    return false;
   e->shape = shape;
+  e->streaming = streaming;
   *key = Key(arch, prec, N, KP, tl);
   return true;
 }
@@ -119,12 +127,12 @@ void append_file_locked(const Key &k, const Entry &e) {
   if (!f) return;  // the in-memory entry still holds
   std::fprintf(f,
                "{\"arch\": \"%s\", \"precision\": %d, \"N\": %d, \"KP\": %d, \"tiles_log2\": %d, "
-               "\"shape\": %d, \"us\": [",
+               "\"shape\": %d, \"streaming\": %d, \"us\": [",
                std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-               std::get<4>(k), e.shape);
+               std::get<4>(k), e.shape, e.streaming);
   for (int s = 0; s < kMaxTileShapes; ++s)
     std::fprintf(f, s ? ", %.3f" : "%.3f", e.us[s]);
-  std::fprintf(f, "]}\n");
+  std::fprintf(f, "], \"us_streaming\": %.3f}\n", e.us_streaming);
   std::fclose(f);
 }
 
@@ -132,7 +140,8 @@ void append_file_locked(const Key &k, const Entry &e) {
 
 int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
                     const std::function<bool(int)> &available,
-                    const std::function<int(int, double *)> &time_shape, int *shape_out) {
+                    const std::function<int(int, bool, double *)> &time_shape, int *shape_out,
+                    bool *streaming_out) {
   const Key key(arch_of(device), mixed ? 1 : 0, N, KP, log2_floor(n_tiles));
   {
     std::lock_guard<std::mutex> lock(g_mu);
@@ -140,6 +149,7 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
     auto it = g_cache.find(key);
     if (it != g_cache.end() && available(it->second.shape)) {
       *shape_out = it->second.shape;
+      *streaming_out = it->second.streaming != 0;
       return HEOM_OK;
     }
   }
@@ -166,15 +176,11 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
     cand[n_cand++] = s;
   }
   if (n_cand == 0) return fail(HEOM_E_UNSUPPORTED, "no tile launch shape for this hierarchy");
-  if (n_cand == 1) {  // nothing to choose
-    *shape_out = cand[0];
-    return HEOM_OK;
-  }
   double best = 0.0;
   for (int q = 0; q < n_cand; ++q) {
     const int s = cand[q];
     double us = 0.0;
-    int rc = time_shape(s, &us);
+    int rc = time_shape(s, false, &us);
     if (rc) return rc;
     e.us[s] = us;
     if (e.shape < 0 || us < best) {
@@ -183,22 +189,30 @@ int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
     }
   }
   if (e.shape < 0) return fail(HEOM_E_UNSUPPORTED, "no tile launch shape for this hierarchy");
+  int rc = time_shape(e.shape, true, &e.us_streaming);  // -1: no such instance
+  if (rc) return rc;
+  e.streaming = e.us_streaming > 0.0 && e.us_streaming < best ? 1 : 0;
   std::lock_guard<std::mutex> lock(g_mu);
   auto ins = g_cache.emplace(key, e);
   if (ins.second) append_file_locked(key, e);
-  *shape_out = available(ins.first->second.shape) ? ins.first->second.shape : e.shape;
+  const Entry &use = available(ins.first->second.shape) ? ins.first->second : e;
+  *shape_out = use.shape;
+  *streaming_out = use.streaming != 0;
   return HEOM_OK;
 }
 
 int autotune_lookup(int device, bool mixed, int N, int KP, int64_t n_tiles, int *shape,
-                    double *us) {
+                    int *streaming, double *us, double *us_streaming) {
   const Key key(arch_of(device), mixed ? 1 : 0, N, KP, log2_floor(n_tiles));
   std::lock_guard<std::mutex> lock(g_mu);
   read_file_locked();
   auto it = g_cache.find(key);
-  *shape = it == g_cache.end() ? -1 : it->second.shape;
+  const bool found = it != g_cache.end();
+  *shape = found ? it->second.shape : -1;
+  if (streaming) *streaming = found ? it->second.streaming : -1;
   if (us)
-    for (int s = 0; s < kMaxTileShapes; ++s) us[s] = it == g_cache.end() ? -1.0 : it->second.us[s];
+    for (int s = 0; s < kMaxTileShapes; ++s) us[s] = found ? it->second.us[s] : -1.0;
+  if (us_streaming) *us_streaming = found ? it->second.us_streaming : -1.0;
   return HEOM_OK;
 }
 

@@ -148,14 +148,19 @@ int build_tables(heom_hierarchy *h);
 // wave, load chunk and minimum waves per SIMD (any output may be NULL).
 bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threads,
                      int *elems_per_wave, int *chunk, int *min_waves);
-// autotune.cpp: the launch shape of a tile group of n_tiles tiles, from the
-// cache or, for a new key, by timing each candidate that available(shape)
-// admits with time_shape(shape, &microseconds_per_launch).
+// kernels_dispatch.hip: whether launch shape `shape` also has an instance
+// with non-temporal (streaming) output stores.
+bool has_streaming_stores(int N, int KP, bool mixed, int shape);
+// autotune.cpp: the launch shape and store policy of a tile group of n_tiles
+// tiles, from the cache or, for a new key, by timing each candidate shape that
+// available(shape) admits with time_shape(shape, streaming = false,
+// &microseconds_per_launch), then the fastest one with streaming stores.
 int autotune_choose(int device, bool mixed, int N, int KP, int64_t n_tiles,
                     const std::function<bool(int)> &available,
-                    const std::function<int(int, double *)> &time_shape, int *shape_out);
+                    const std::function<int(int, bool, double *)> &time_shape, int *shape_out,
+                    bool *streaming_out);
 int autotune_lookup(int device, bool mixed, int N, int KP, int64_t n_tiles, int *shape,
-                    double *us);
+                    int *streaming, double *us, double *us_streaming);
 void autotune_clear();
 
 }  // namespace heom

@@ -5,45 +5,45 @@
 
 namespace heom {
 
-typedef StageKernel (*TilePart)(int N, int KP, bool mixed);
+typedef StageKernel (*TilePart)(int N, int KP, bool mixed, bool streaming);
 // Tile instances by shape and storage precision (_f1: FP64, _f0: FP32-mixed):
 // N <= 8 in every shape, N = 9..12 in shape 0 only.
-StageKernel tile_kernel_part_small_s0_f1(int, int, bool);
-StageKernel tile_kernel_part_small_s0_f0(int, int, bool);
-StageKernel tile_kernel_part_7_s0_f1(int, int, bool);
-StageKernel tile_kernel_part_7_s0_f0(int, int, bool);
-StageKernel tile_kernel_part_8_s0_f1(int, int, bool);
-StageKernel tile_kernel_part_8_s0_f0(int, int, bool);
-StageKernel tile_kernel_part_9_10_s0_f1(int, int, bool);
-StageKernel tile_kernel_part_9_10_s0_f0(int, int, bool);
-StageKernel tile_kernel_part_11_s0_f1(int, int, bool);
-StageKernel tile_kernel_part_11_s0_f0(int, int, bool);
-StageKernel tile_kernel_part_12_s0_f1(int, int, bool);
-StageKernel tile_kernel_part_12_s0_f0(int, int, bool);
-StageKernel tile_kernel_part_small_s1_f1(int, int, bool);
-StageKernel tile_kernel_part_small_s1_f0(int, int, bool);
-StageKernel tile_kernel_part_7_s1_f1(int, int, bool);
-StageKernel tile_kernel_part_7_s1_f0(int, int, bool);
-StageKernel tile_kernel_part_8_s1_f1(int, int, bool);
-StageKernel tile_kernel_part_8_s1_f0(int, int, bool);
-StageKernel tile_kernel_part_small_s2_f1(int, int, bool);
-StageKernel tile_kernel_part_small_s2_f0(int, int, bool);
-StageKernel tile_kernel_part_7_s2_f1(int, int, bool);
-StageKernel tile_kernel_part_7_s2_f0(int, int, bool);
-StageKernel tile_kernel_part_8_s2_f1(int, int, bool);
-StageKernel tile_kernel_part_8_s2_f0(int, int, bool);
-StageKernel tile_kernel_part_small_s3_f1(int, int, bool);
-StageKernel tile_kernel_part_small_s3_f0(int, int, bool);
-StageKernel tile_kernel_part_7_s3_f1(int, int, bool);
-StageKernel tile_kernel_part_7_s3_f0(int, int, bool);
-StageKernel tile_kernel_part_8_s3_f1(int, int, bool);
-StageKernel tile_kernel_part_8_s3_f0(int, int, bool);
-StageKernel tile_kernel_part_small_s4_f1(int, int, bool);
-StageKernel tile_kernel_part_small_s4_f0(int, int, bool);
-StageKernel tile_kernel_part_7_s4_f1(int, int, bool);
-StageKernel tile_kernel_part_7_s4_f0(int, int, bool);
-StageKernel tile_kernel_part_8_s4_f1(int, int, bool);
-StageKernel tile_kernel_part_8_s4_f0(int, int, bool);
+StageKernel tile_kernel_part_small_s0_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s0_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s0_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s0_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s0_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s0_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_9_10_s0_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_9_10_s0_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_11_s0_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_11_s0_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_12_s0_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_12_s0_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s1_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s1_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s1_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s1_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s1_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s1_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s2_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s2_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s2_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s2_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s2_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s2_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s3_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s3_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s3_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s3_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s3_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s3_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s4_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s4_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s4_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_7_s4_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s4_f1(int, int, bool, bool);
+StageKernel tile_kernel_part_8_s4_f0(int, int, bool, bool);
 StageKernel lane_kernel_ptr(int N, int KP, bool mixed);
 
 namespace {
@@ -68,16 +68,20 @@ constexpr TilePart kTileParts[kTileShapes][12] = {
      nullptr, nullptr, nullptr, nullptr, nullptr},
 };
 
-StageKernel tile_kernel(int N, int KP, bool mixed, int shape) {
+StageKernel tile_kernel(int N, int KP, bool mixed, int shape, bool streaming = false) {
   if (shape < 0 || shape >= kTileShapes) return nullptr;
   for (TilePart part : kTileParts[shape]) {
-    StageKernel k = part ? part(N, KP, mixed) : nullptr;
+    StageKernel k = part ? part(N, KP, mixed, streaming) : nullptr;
     if (k) return k;
   }
   return nullptr;
 }
 
 }  // namespace
+
+bool has_streaming_stores(int N, int KP, bool mixed, int shape) {
+  return shape != kWideShape && tile_kernel(N, KP, mixed, shape, true) != nullptr;
+}
 
 bool has_fixed_kernel(int N, int KP) { return lane_kernel_ptr(N, KP, false) != nullptr; }
 
@@ -142,9 +146,13 @@ hipError_t prepare_wide(int N, int M, bool mixed) {
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// `streaming` selects the tile kernel instance with non-temporal output
+// stores (built for FP64 storage; the wide, lane and generic kernels always
+// store plainly).
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
-                        int stage, double coef, int hist_slot, hipStream_t stream) {
+                        int stage, double coef, int hist_slot, bool streaming,
+                        hipStream_t stream) {
   if (kind == KernelKind::kTile && shape == kWideShape) {
     const size_t lds = static_cast<size_t>(wide_lds(N, N * KP, mixed ? 4 : 8).total);
     const StageKernel k = reinterpret_cast<StageKernel>(
@@ -157,7 +165,7 @@ hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
   StageKernel k = nullptr;
   switch (kind) {
     case KernelKind::kTile:
-      k = tile_kernel(N, KP, mixed, shape);
+      k = tile_kernel(N, KP, mixed, shape, streaming);
       break;
     case KernelKind::kLane:
       k = lane_kernel_ptr(N, KP, mixed);

@@ -1,18 +1,18 @@
 // kernels_tile_9_10.hip -- instances of the tile stage kernel for
 // N=9 K+1=1, N=10 K+1=1
-// in launch shape HEOM_SHAPE and storage precision HEOM_TILE_F64 (FP64 or
-// FP32-mixed): the unit is compiled once per shape it provides and per
-// precision.
+// in launch shape HEOM_SHAPE and storage precision HEOM_TILE_F64 (FP64, with
+// plain and streaming stores, or FP32-mixed): the unit is compiled once per
+// shape it provides and per precision.
 #include "stage_kernels.h"
 
 namespace heom {
 
-StageKernel HEOM_SHAPED(tile_kernel_part_9_10)(int N, int KP, bool mixed) {
+StageKernel HEOM_SHAPED(tile_kernel_part_9_10)(int N, int KP, bool mixed, bool streaming) {
   constexpr int S = HEOM_SHAPE;
   if (N == 9 && KP == 1)
-    return tile_instance<9, 1, S>(mixed);
+    return tile_instance<9, 1, S>(mixed, streaming);
   if (N == 10 && KP == 1)
-    return tile_instance<10, 1, S>(mixed);
+    return tile_instance<10, 1, S>(mixed, streaming);
   return nullptr;
 }
 

@@ -27,7 +27,8 @@ bool has_fixed_kernel(int N, int KP);
 hipError_t prepare_wide(int N, int M, bool mixed);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
-                        int stage, double coef, int hist_slot, hipStream_t stream);
+                        int stage, double coef, int hist_slot, bool streaming,
+                        hipStream_t stream);
 hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
                        int block, hipStream_t stream);
 hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
@@ -315,6 +316,7 @@ struct Group {
   KernelKind kind;
   int N, KP;
   int shape;    // launch shape (kTile only)
+  bool streaming = false;  // non-temporal output stores (kTile only)
   int threads;  // of the chosen shape
   int64_t n_tiles;  // 64-ADO tiles of the group (the autotuner's size key)
   int64_t begin[2] = {0, 0}, count[2] = {0, 0};  // work lists: [0] 64-ADO, [1] 16-ADO items
@@ -346,6 +348,14 @@ constexpr int kTuneReps = 5;
 // Tile launch shape forced by the flags (HEOM_TILE_SHAPE(s)), or -1.
 int forced_shape(int flags) { return ((flags >> 8) & 0xf) - 1; }
 
+// Store policy of the tile kernels forced by the flags: 1 streaming (where
+// such an instance is built), 0 plain, -1 not forced.
+int forced_streaming(int flags) {
+  if (flags & HEOM_STREAMING_STORES) return 1;
+  if (flags & HEOM_PLAIN_STORES) return 0;
+  return -1;
+}
+
 constexpr int kShapeFlagMask = 0xf00;
 
 // Where the device data of one call live: each instance's regions (offsets
@@ -371,6 +381,8 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
   if (flags & ~allowed_flags) return fail(HEOM_E_INVALID, "unknown flags");
   if ((flags & HEOM_GENERIC_KERNEL) && (flags & HEOM_LANE_KERNEL))
     return fail(HEOM_E_INVALID, "HEOM_GENERIC_KERNEL and HEOM_LANE_KERNEL are exclusive");
+  if ((flags & HEOM_STREAMING_STORES) && (flags & HEOM_PLAIN_STORES))
+    return fail(HEOM_E_INVALID, "HEOM_STREAMING_STORES and HEOM_PLAIN_STORES are exclusive");
   if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(HEOM_E_INVALID, "dt_fs must be > 0");
   if (n_steps < 0) return fail(HEOM_E_INVALID, "n_steps must be >= 0");
   if (record_every < 1) return fail(HEOM_E_INVALID, "record_every must be >= 1");
@@ -604,17 +616,24 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     ++slot;
   }
   const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
-  // Launch shape of each tile group: forced by the flags, the default, or
-  // the autotuner's.  The tuner times repeated stage sequences 1, 2, 3, 2:
+  // Launch shape and store policy of each tile group: forced by the flags,
+  // the defaults (plain stores), or the autotuner's.  A store policy forced
+  // by the flags overrides the tuner's.  The tuner times repeated stage
+  // sequences 1, 2, 3, 2:
   // the same traffic as a step, but none of them writes the state y (only
   // the last stage does), and the run's first step rewrites the stage
   // buffers they leave behind before reading them, so the run is unchanged.
   for (Group &g : groups) {
     if (g.kind != KernelKind::kTile) continue;
     int shape = forced_shape(flags);  // validated by check_common
+    bool streaming = false;
     if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = g.shape;
     if (shape < 0) {
-      auto time_shape = [&](int s, double *us) -> int {
+      auto time_shape = [&](int s, bool nt, double *us) -> int {
+        if (nt && !has_streaming_stores(g.N, g.KP, mixed, s)) {
+          *us = -1.0;  // not built
+          return HEOM_OK;
+        }
         int threads = 0;
         tile_shape_info(g.N, g.KP, mixed, s, nullptr, &threads, nullptr, nullptr, nullptr);
         const int l = g.list(s);
@@ -625,7 +644,8 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
           for (int st : {0, 1, 2, 1})
             if (e == hipSuccess)
               e = launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.begin[l],
-                               static_cast<int>(g.count[l]), threads, st, coef[st], -1, stream);
+                               static_cast<int>(g.count[l]), threads, st, coef[st], -1, nt,
+                               stream);
           return e;
         };
         hipError_t e = hipEventCreate(&ev[0]);
@@ -645,10 +665,13 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       };
       // A shape is available when the group carries the work list it uses.
       auto available = [&](int s) { return g.count[g.list(s)] > 0; };
-      int rc = autotune_choose(device, mixed, g.N, g.KP, g.n_tiles, available, time_shape, &shape);
+      int rc = autotune_choose(device, mixed, g.N, g.KP, g.n_tiles, available, time_shape, &shape,
+                               &streaming);
       if (rc) return rc;
     }
+    if (forced_streaming(flags) >= 0) streaming = forced_streaming(flags) == 1;
     g.shape = shape;
+    g.streaming = streaming && has_streaming_stores(g.N, g.KP, mixed, shape);
     tile_shape_info(g.N, g.KP, mixed, shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
   }
   // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.  With
@@ -663,7 +686,8 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   auto launch_group = [&](const Group &g, int st, hipStream_t s) -> hipError_t {
     const int l = g.list(g.shape);
     return launch_stage(g.kind, mixed, g.N, g.KP, g.shape, d_descs, d_work + g.begin[l],
-                        static_cast<int>(g.count[l]), g.threads, st, coef[st], -1, s);
+                        static_cast<int>(g.count[l]), g.threads, st, coef[st], -1, g.streaming,
+                        s);
   };
   auto enqueue_step = [&](hipStream_t s) -> hipError_t {
     for (int st = 0; st < 4; ++st) {
@@ -747,7 +771,8 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
                    double *const *sinks_outs) {
   int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, record_every,
                         HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
-                            HEOM_NO_AUTOTUNE | kShapeFlagMask);
+                            HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
+                            kShapeFlagMask);
   if (rc) return rc;
   const Layout L = make_layout(hs, n, precision);
   if (!d_ws) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
@@ -933,7 +958,8 @@ int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int 
   try {
     int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, 1,
                           HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
-                              HEOM_NO_AUTOTUNE | kShapeFlagMask);
+                              HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
+                              kShapeFlagMask);
     if (rc) return rc;
     if (!d_workspaces || !workspace_bytes || !start)
       return fail(HEOM_E_INVALID, "workspaces, sizes and start flags are required");
@@ -1117,18 +1143,20 @@ int heom_tile_shape_info(int32_t n_sites, int32_t modes_per_site, int precision,
 }
 
 int heom_autotune_lookup(int32_t n_sites, int32_t modes_per_site, int precision, int64_t n_tiles,
-                         int32_t *shape, double *us_per_shape) {
+                         int32_t *shape, double *us_per_shape, int32_t *streaming,
+                         double *us_streaming) {
   if (!shape) return fail(HEOM_E_INVALID, "shape is NULL");
   if (precision != HEOM_FP64 && precision != HEOM_FP32_MIXED)
     return fail(HEOM_E_UNSUPPORTED, "precision must be HEOM_FP64 or HEOM_FP32_MIXED");
   if (n_tiles < 1) return fail(HEOM_E_INVALID, "n_tiles must be >= 1");
   int device = 0;
   HEOM_HIP(hipGetDevice(&device), "hipGetDevice");
-  int s = -1;
+  int s = -1, nt = -1;
   int rc = autotune_lookup(device, precision == HEOM_FP32_MIXED, n_sites, modes_per_site, n_tiles,
-                           &s, us_per_shape);
+                           &s, &nt, us_per_shape, us_streaming);
   if (rc) return rc;
   *shape = s;
+  if (streaming) *streaming = nt;
   return HEOM_OK;
 }
 

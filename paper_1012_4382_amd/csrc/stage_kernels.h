@@ -92,9 +92,19 @@ template <typename T>
 __device__ __forceinline__ T ld_off(const HEOM_GLOBAL T *base, uint32_t off) {
   return *(const HEOM_GLOBAL T *)((const HEOM_GLOBAL char *)base + off);
 }
-template <typename T>
+// STREAM marks the store non-temporal.  On gfx950 that shortens small,
+// latency-bound FP64 stage launches (by about 8 % at 432 tiles) and lengthens
+// large, bandwidth-bound ones (by 6-11 % at 3500 tiles and more), so the FP64
+// tile kernels are built both ways and the autotuner picks per launch size.
+// (A run-time choice between the two stores does not work: the compiler
+// merges them into one plain store.)
+template <bool STREAM, typename T>
 __device__ __forceinline__ void st_off(HEOM_GLOBAL T *base, uint32_t off, T v) {
-  *(HEOM_GLOBAL T *)((HEOM_GLOBAL char *)base + off) = v;
+  HEOM_GLOBAL T *p = (HEOM_GLOBAL T *)((HEOM_GLOBAL char *)base + off);
+  if constexpr (STREAM)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // Buffers used by stage s.
@@ -732,7 +742,7 @@ __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> 
 
 // Phase 2 of element (A, B): right-hand side from the LDS tile and the loaded
 // values, RK4 stage update, store.  C is the arithmetic type.
-template <int N, int KP, int A, int B, typename C, typename T>
+template <int N, int KP, int A, int B, typename C, typename T, bool STREAM>
 __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads<C, KP> &L) {
 #pragma clang fp contract(off)
   constexpr int M = N * KP;
@@ -794,22 +804,23 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
   // In FP32-mixed runs sigma_0 is written by tile_sigma0 alone.
   if (sizeof(T) == 4 && c.i == 0) return;
   const uint32_t oi = static_cast<uint32_t>(c.i) * sizeof(T);
-  st_off(c.Out + E * c.S, oi, static_cast<T>(nr));
-  if constexpr (A != B) st_off(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
+  st_off<STREAM>(c.Out + E * c.S, oi, static_cast<T>(nr));
+  if constexpr (A != B) st_off<STREAM>(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
 }
 
 // One chunk of wave G's elements (element indices OFF + K): all global loads
 // first, then arithmetic and stores.
-template <int N, int KP, int G, int W, int OFF, typename C, typename T, int... K>
+template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool STREAM, int... K>
 __device__ __forceinline__ void tile_chunk(const TileCtx<T> &c, std::integer_sequence<int, K...>) {
   ElemLoads<C, KP> L[sizeof...(K)];
   (tile_load<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T>(c, L[K]),
    ...);
-  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T>(c, L[K]),
+  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, STREAM>(
+       c, L[K]),
    ...);
 }
 
-template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T>
+template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T, bool STREAM>
 __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int P = N * (N + 1) / 2;
   constexpr int count = (P - G + W - 1) / W;
@@ -818,25 +829,25 @@ __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int CH = CH0 / KP > 0 ? CH0 / KP : 1;
   if constexpr (OFF < count) {
     constexpr int len = (count - OFF < CH) ? count - OFF : CH;
-    tile_chunk<N, KP, G, W, OFF, C, T>(c, std::make_integer_sequence<int, len>{});
+    tile_chunk<N, KP, G, W, OFF, C, T, STREAM>(c, std::make_integer_sequence<int, len>{});
     // Keep the next chunk's LDS reads from being hoisted above this chunk
     // (they cannot alias its global stores), which would hold every operand
     // of the wave's elements in registers at once.
 #if HEOM_TILE_CHUNK_BARRIER
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T>(c);
+    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T, STREAM>(c);
   }
 }
 
 // Elements G, G + W, ... of every ADO of the tile (wave G of W).
-template <int N, int KP, int W, int CH0, typename C, typename T, int G = 0>
+template <int N, int KP, int W, int CH0, typename C, typename T, bool STREAM, int G = 0>
 __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
   if constexpr (G < W) {
     if (wave == G)
-      tile_chunks<N, KP, G, W, CH0, 0, C, T>(c);
+      tile_chunks<N, KP, G, W, CH0, 0, C, T, STREAM>(c);
     else
-      tile_dispatch<N, KP, W, CH0, C, T, G + 1>(wave, c);
+      tile_dispatch<N, KP, W, CH0, C, T, STREAM, G + 1>(wave, c);
   }
 }
 
@@ -939,7 +950,7 @@ __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
   }
 }
 
-template <int N, int KP, typename T, int SHAPE>
+template <int N, int KP, typename T, int SHAPE, bool STREAM>
 __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                                   tile_shape(sizeof(T) == 8, SHAPE).min_waves)
     stage_tile(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
@@ -1080,17 +1091,20 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   for (int m = 0; m < M; ++m)
     ctx.damp = fmad(static_cast<double>(socc[m * kTile + lane]), P[2 * N * N + 4 * N + 2 * M + m],
                     ctx.damp);
-  tile_dispatch<N, KP, W, CH0, T, T>(wave, ctx);
+  tile_dispatch<N, KP, W, CH0, T, T, STREAM>(wave, ctx);
 }
 
-// The instance of a tile unit for storage `mixed`: null for the precision the
-// unit is not compiled for (the other unit of the same shape provides it).
+// The instance of a tile unit for storage `mixed` and the store policy: null
+// for the precision the unit is not compiled for (the other unit of the same
+// shape provides it), and for streaming stores in FP32-mixed storage (not
+// built: at most 1 % faster there, on small launches only).
 template <int N, int KP, int S>
-StageKernel tile_instance(bool mixed) {
+StageKernel tile_instance(bool mixed, bool streaming) {
 #if HEOM_TILE_F64
-  return mixed ? nullptr : &stage_tile<N, KP, double, S>;
+  if (mixed) return nullptr;
+  return streaming ? &stage_tile<N, KP, double, S, true> : &stage_tile<N, KP, double, S, false>;
 #else
-  return mixed ? &stage_tile<N, KP, float, S> : nullptr;
+  return mixed && !streaming ? &stage_tile<N, KP, float, S, false> : nullptr;
 #endif
 }
 
@@ -1307,8 +1321,8 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
   }
   const uint32_t sz = static_cast<uint32_t>(sizeof(T));
   const uint32_t oi = static_cast<uint32_t>(c.i) * sz;
-  st_off(c.Out, static_cast<uint32_t>(E) * c.S * sz + oi, static_cast<T>(nr));
-  if (offd) st_off(c.Out, static_cast<uint32_t>(E + 1) * c.S * sz + oi, static_cast<T>(ni));
+  st_off<false>(c.Out, static_cast<uint32_t>(E) * c.S * sz + oi, static_cast<T>(nr));
+  if (offd) st_off<false>(c.Out, static_cast<uint32_t>(E + 1) * c.S * sz + oi, static_cast<T>(ni));
 }
 
 template <typename T, int KP>

@@ -31,7 +31,10 @@ HEOM_GENERIC_KERNEL = 2
 HEOM_LANE_KERNEL = 4
 HEOM_NO_GRAPH = 8
 HEOM_NO_AUTOTUNE = 16
+HEOM_STREAMING_STORES = 32
+HEOM_PLAIN_STORES = 64
 KERNELS = {"auto": 0, "generic": HEOM_GENERIC_KERNEL, "lane": HEOM_LANE_KERNEL}
+STORES = {None: 0, "streaming": HEOM_STREAMING_STORES, "plain": HEOM_PLAIN_STORES}
 
 
 def tile_shape_flag(shape: int) -> int:
@@ -39,8 +42,10 @@ def tile_shape_flag(shape: int) -> int:
     return ((int(shape) + 1) & 0xF) << 8
 
 
-def _flags(resume: bool, kernel: str, graphs: bool, tile_shape, autotune: bool) -> int:
+def _flags(resume: bool, kernel: str, graphs: bool, tile_shape, autotune: bool,
+           stores=None) -> int:
     f = (HEOM_RESUME if resume else 0) | KERNELS[kernel] | (0 if graphs else HEOM_NO_GRAPH)
+    f |= STORES[stores]
     if tile_shape is not None:
         f |= tile_shape_flag(tile_shape)
     elif not autotune:
@@ -105,7 +110,8 @@ _SIGNATURES = [
     ("heom_tile_shape_count", ctypes.c_int, []),
     ("heom_tile_shape_info", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i32, _P(_i32), _P(_i32),
                                             _P(_i32), _P(_i32), _P(_i32)]),
-    ("heom_autotune_lookup", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i64, _P(_i32), _P(_d)]),
+    ("heom_autotune_lookup", ctypes.c_int,
+     [_i32, _i32, ctypes.c_int, _i64, _P(_i32), _P(_d), _P(_i32), _P(_d)]),
     ("heom_autotune_clear", None, []),
     ("heom_destroy", None, [_vp]),
     ("heom_status_string", ctypes.c_char_p, [ctypes.c_int]),
@@ -246,15 +252,16 @@ def _ws_args(ws):
 def propagate(h: Hierarchy, rho0, dt_fs: float, n_steps: int, record_every: int = 1,
               precision="fp64", workspace=None, stream=None, resume: bool = False,
               kernel: str = "auto", want_rho: bool = True, graphs: bool = True,
-              tile_shape=None, autotune: bool = True):
+              tile_shape=None, autotune: bool = True, stores=None):
     """Runs heom_propagate (kernel: "auto", or the diagnostic "lane" / "generic";
-    tile_shape forces a tile launch shape, autotune=False uses shape 0).
+    tile_shape forces a tile launch shape, autotune=False uses shape 0; stores
+    "streaming" / "plain" forces the tile kernels' store policy).
     Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(h.workspace_bytes[prec])
     ptr, nbytes = _ws_args(workspace)
-    flags = _flags(resume, kernel, graphs, tile_shape, autotune)
+    flags = _flags(resume, kernel, graphs, tile_shape, autotune, stores)
     r0 = None
     if rho0 is not None:
         r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
@@ -279,14 +286,14 @@ def batch_workspace_bytes(hs, precision="fp64") -> int:
 def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1,
                     precision="fp64", workspace=None, stream=None, resume: bool = False,
                     kernel: str = "auto", want_rho: bool = True, graphs: bool = True,
-                    tile_shape=None, autotune: bool = True):
+                    tile_shape=None, autotune: bool = True, stores=None):
     """Runs heom_propagate_batch.  Returns (list of rho | None, sinks [n, 3], workspace)."""
     n = len(hs)
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(batch_workspace_bytes(hs, precision))
     ptr, nbytes = _ws_args(workspace)
-    flags = _flags(resume, kernel, graphs, tile_shape, autotune)
+    flags = _flags(resume, kernel, graphs, tile_shape, autotune, stores)
     DP = ctypes.POINTER(ctypes.c_double)
     keep = []
     r0 = (DP * n)()
@@ -345,7 +352,8 @@ def slots_scratch_bytes(hs) -> int:
 
 def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scratch,
                   precision="fp64", stream=None, kernel: str = "auto", graphs: bool = True,
-                  want_rho: bool = True, tile_shape=None, autotune: bool = True):
+                  want_rho: bool = True, tile_shape=None, autotune: bool = True,
+                  stores=None):
     """Runs heom_advance_slots.  Returns (list of final rho [N, N] | None, sinks [n, 3])."""
     n = len(hs)
     DP = ctypes.POINTER(ctypes.c_double)
@@ -368,7 +376,7 @@ def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scra
         so[k] = sinks[k].ctypes.data_as(DP)
     arr = (ctypes.c_void_p * n)(*[h.handle.value for h in hs])
     sptr, sbytes = _ws_args(scratch)
-    flags = _flags(False, kernel, graphs, tile_shape, autotune)
+    flags = _flags(False, kernel, graphs, tile_shape, autotune, stores)
     _check(library().heom_advance_slots(arr, n, PRECISIONS[precision], flags, wsp, wsb, st, r0,
                                         float(dt_fs), int(n_steps), sptr, sbytes,
                                         _stream_handle(stream), ro, so), "heom_advance_slots")
@@ -394,14 +402,17 @@ def tile_shape_info(n_sites: int, modes_per_site: int, precision="fp64", shape: 
 
 
 def autotune_lookup(n_sites: int, modes_per_site: int, n_tiles: int, precision="fp64"):
-    """(tuned shape or -1, microseconds per stage launch of each shape,
-    -1 where not timed) for the current device."""
-    shape = ctypes.c_int32()
-    us = np.full(tile_shape_count(), -1.0)
+    """(tuned shape or -1, microseconds per stage launch of each shape with
+    plain stores, -1 where not timed, streaming stores chosen (1 / 0, -1 if
+    not tuned), microseconds of the tuned shape with streaming stores) for
+    the current device."""
+    shape, streaming = ctypes.c_int32(), ctypes.c_int32()
+    us, us_streaming = np.full(tile_shape_count(), -1.0), ctypes.c_double()
     _check(library().heom_autotune_lookup(int(n_sites), int(modes_per_site),
                                           PRECISIONS[precision], int(n_tiles),
-                                          ctypes.byref(shape), _dp(us)), "heom_autotune_lookup")
-    return shape.value, us
+                                          ctypes.byref(shape), _dp(us), ctypes.byref(streaming),
+                                          ctypes.byref(us_streaming)), "heom_autotune_lookup")
+    return shape.value, us, streaming.value, us_streaming.value
 
 
 def autotune_clear():

@@ -154,19 +154,27 @@ def test_autotuner_choice_is_cached_and_leaves_the_run_unchanged(precision):
     _say(f"case: autotune fmo_like batch of 4, depth 5, {precision}")
     tuned, s_tuned, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5,
                                              precision=precision)
-    shape, us = heom.autotune_lookup(7, 1, n_tiles, precision)
+    shape, us, streaming, us_streaming = heom.autotune_lookup(7, 1, n_tiles, precision)
     assert 0 <= shape < heom.tile_shape_count()
     timed = us[us >= 0]
     assert len(timed) >= 2 and np.all(timed > 0) and us[shape] == np.min(timed)
-    _say(f"  tuned shape {shape}, us per stage launch {us.tolist()}")
+    # The chosen shape is timed again with streaming stores where that instance
+    # is built (FP64 tile shapes); the faster wins.
+    if us_streaming > 0:
+        assert precision == "fp64" and streaming == (1 if us_streaming < us[shape] else 0)
+    else:
+        assert us_streaming == -1 and streaming == 0 and (precision == "fp32" or shape == 5)
+    _say(f"  tuned shape {shape}, us per stage launch {us.tolist()}, "
+         f"streaming stores {streaming} ({us_streaming:.3f} us)")
     plain, s_plain, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5,
                                              precision=precision, autotune=False)
     for a, b in zip(tuned, plain):
         assert np.array_equal(a, b)
     assert np.array_equal(s_tuned, s_plain)
     again, _, _ = heom.propagate_batch(hs, r0, 1.0, 100, record_every=5, precision=precision)
-    shape2, us2 = heom.autotune_lookup(7, 1, n_tiles, precision)
+    shape2, us2, streaming2, us_streaming2 = heom.autotune_lookup(7, 1, n_tiles, precision)
     assert shape2 == shape and np.array_equal(us2, us)  # not re-timed
+    assert (streaming2, us_streaming2) == (streaming, us_streaming)
     for a, b in zip(again, plain):
         assert np.array_equal(a, b)
 
@@ -185,14 +193,42 @@ def test_autotune_cache_file(tmp_path, monkeypatch):
         entry = json.loads(lines[0])
         assert (entry["N"], entry["KP"], entry["precision"], entry["tiles_log2"]) == (7, 1, 0, 1)
         assert entry["shape"] == heom.autotune_lookup(7, 1, 2)[0]
-        # An entry in the file is used as it stands (here: shape 2) and not re-timed.
-        entry["shape"] = 2
+        assert entry["streaming"] == heom.autotune_lookup(7, 1, 2)[2]
+        # An entry in the file is used as it stands (here: shape 2 with
+        # streaming stores) and not re-timed.
+        entry["shape"], entry["streaming"] = 2, 1
         path.write_text(json.dumps(entry) + "\n")
         heom.autotune_clear()
-        assert heom.autotune_lookup(7, 1, 2)[0] == 2
+        assert heom.autotune_lookup(7, 1, 2)[0:3:2] == (2, 1)
         rho2, _, _ = heom.propagate(h, w["rho0"], 1.0, 64, record_every=8)
         assert len(path.read_text().splitlines()) == 1
         assert np.array_equal(rho, rho2)
     finally:
         monkeypatch.delenv("HEOM_AUTOTUNE_CACHE")
         heom.autotune_clear()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_store_policies_give_identical_results(precision):
+    """Streaming (non-temporal) and plain output stores, forced per call, in a
+    tile shape and in the wide kernel (which, like the FP32-mixed tile kernels,
+    has no streaming instance and stores plainly): bitwise the same run, and
+    the oracle's."""
+    w = workloads.fmo_like(seed=0, site=6, depth=3, steps=300)
+    h = heom.Hierarchy(w["system"], w["depth"])
+    ref = oracle.propagate(w["system"], w["depth"], w["rho0"], 1.0, 300, record_every=10)
+    for s in (3, 5):
+        runs = []
+        for stores in ("plain", "streaming"):
+            _say(f"case: fmo_like seed0 site6 depth3 300 steps {precision} shape={s} {stores}")
+            rho, sinks, _ = heom.propagate(h, w["rho0"], 1.0, 300, record_every=10,
+                                           precision=precision, tile_shape=s, stores=stores)
+            runs.append((rho, sinks))
+        assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+        rho, sinks = runs[1]
+        if precision == "fp64":
+            assert float(np.max(np.abs(rho - ref["rho"])) / np.max(np.abs(ref["rho"]))) <= 1e-10
+            assert np.max(np.abs(sinks - ref["scalars"])) <= 1e-10
+        else:
+            assert np.max(np.abs(rho - ref["rho"])) <= 1e-5
+            assert abs(sinks[0] - ref["scalars"][0]) <= 1e-5
