@@ -9,9 +9,9 @@
 // choice on (GPU architecture, precision, N, K+1, floor(log2(tiles))), times
 // every candidate once per key on the caller's own launch (see run_impl),
 // then the fastest one again with non-temporal (streaming) output stores, and
-// remembers the faster configuration for the life of the process.  If HEOM_AUTOTUNE_CACHE
-// names a file, its entries are read on first use and new entries are
-// appended to it, one JSON object per line.
+// remembers the faster configuration for the life of the process.  If
+// HEOM_AUTOTUNE_CACHE names a file, its entries are read on first use and new
+// entries are appended to it, one JSON object per line.
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
