@@ -247,6 +247,26 @@ def test_batch_equals_single_solves(precision, kernel):
         assert np.array_equal(sinks[k], s1), k
 
 
+def test_benchmark_batch_launch_against_oracle():
+    """The benchmarked launch itself: the 8-solve FMO-shaped batch (8 x 3432
+    ADOs, 432 tiles) in the launch shape and store policy the autotuner picks
+    for it, recording every 10 steps as the benchmark does; 40 steps of every
+    solve against the oracle, element by element."""
+    ws_ = workloads.fmo_like_batch()
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in ws_]
+    assert sum(h.n_ados for h in hs) == 27456
+    _say("case: benchmark batch, 8 solves x 3432 ADOs, autotuned, 40 steps vs oracle")
+    rhos, sinks, _ = heom.propagate_batch(hs, [w["rho0"] for w in ws_], 1.0, 40, record_every=10)
+    shape, _, streaming, _ = heom.autotune_lookup(7, 1, 432, "fp64")
+    _say(f"  tuned launch: shape {shape}, streaming stores {streaming}")
+    assert shape >= 0
+    for k, w in enumerate(ws_):
+        ref = oracle.propagate(w["system"], w["depth"], w["rho0"], 1.0, 40, record_every=10)
+        assert _rel(rhos[k], ref["rho"]) <= FP64_TOL, k
+        assert abs(sinks[k][0] - ref["scalars"][0]) <= FP64_TOL * abs(ref["scalars"][0]), k
+        assert np.max(np.abs(sinks[k] - ref["scalars"])) <= FP64_TOL, k
+
+
 def test_resume_is_bitwise_identical():
     w = workloads.fmo_like(seed=2, site=6, depth=4, steps=300)
     _say("case: resume 100 + 200 vs 300 steps")
