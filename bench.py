@@ -1,27 +1,37 @@
 """Throughput benchmark of the HEOM propagation on one MI355X.
 
 One benchmark step is one pass of the whole hot path over one batch of
-synthetic input: the FMO-shaped 7-site workload at hierarchy depth 7 (3432
-ADOs per solve), all 8 solves (Hamiltonian seeds 0-3, excitation starting at
-site 1 or site 6), each propagated 5000 RK4 steps of 1 fs (5 ps) in FP64 with
-trapping and recombination sinks, as one batched launch sequence.  Inputs,
-tables and parameters are on the device before the timed region starts.
+synthetic input: the batched parameter sweep, 64 instances of the 7-site
+FMO-shaped system, each with its own Hamiltonian, bath (lambda, 1/gamma, T),
+one Matsubara term per bath (14 bath modes) and hierarchy depth 3-5 (680 to
+11628 ADOs, 381956 in all, 449 MB of FP64 state, beyond the 256 MB Infinity
+Cache), propagated 1000 RK4 steps of 1 fs in FP64 with trapping and
+recombination sinks, sigma_0 recorded every 100 steps, as one batched launch
+sequence.  Inputs, tables and parameters are on the device before the timed
+region starts.
 
 Printed: one JSON line with ADO-steps/s (whole job), the roofline of the
-dominant kernel (on the classic RK4 algorithmic bytes and on the bytes the
-nested form moves, with the counted traffic of the committed profile), and the
-oracle timed on this host on a bounded sample.  Further legs, each skippable:
-single-solve and FP32-mixed rates, the depth-16 and 24-site sizing launches,
-batch scaling (2-128 solves, and a plain device copy for scale), the
-64-instance parameter sweep, the precision comparison, and serving.
+dominant kernel from HIP events around the timed launches themselves (on the
+classic RK4 algorithmic bytes, on the bytes the nested form moves, and on the
+counted traffic of the committed rocprofv3 profile), the check of the timed
+runs against the oracle's stored trajectories, and the oracle timed on this
+host (1 thread and all threads) on a bounded sample.  Further legs, each
+skippable: the FMO-shaped 8-solve batch at depth 7 (5 ps, eta) with its own
+roofline, single-solve and FP32-mixed rates, the depth-16 and 24-site sizing
+launches, batch scaling (2-128 solves and a plain device copy for scale), the
+precision comparison against the oracle, and the 200-request serving trace in
+FP64 and FP32-mixed.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
+import subprocess
 import sys
 import time
+from math import comb
 
 import numpy as np
 
@@ -32,6 +42,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # moves 11 per step (11/4 per stage); both rates are reported.
 ALG_ADOS_PER_LAUNCH = 4.0
 MOVED_ADOS_PER_LAUNCH = 11.0 / 4.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+# rocprofv3 summaries of the dominant kernels (FETCH_SIZE / WRITE_SIZE
+# traffic), and the sources whose digest they record.
+PROFILES = {"sweep": os.path.join(ROOT, "profiles", "stage_tile_7_k1_fp64_sweep64.md"),
+            "fmo": os.path.join(ROOT, "profiles", "stage_tile_7_fp64_fmo_batch.md")}
+KERNEL_SOURCES = ["paper_1012_4382_amd/csrc/stage_kernels.h",
+                  "paper_1012_4382_amd/csrc/heom_internal.h",
+                  "paper_1012_4382_amd/csrc/kernels_tile_7.hip", "paper_1012_4382_amd/build.py"]
 
 
 def _rates(n_ados, N, s, k_ms):
@@ -41,13 +60,6 @@ def _rates(n_ados, N, s, k_ms):
     moved = n_ados * MOVED_ADOS_PER_LAUNCH * N * N * s / (k_ms * 1e-3) / 1e9
     return {"achieved_GBps": alg, "frac_of_hbm_peak": alg / HBM_PEAK_GBS,
             "moved_GBps": moved, "moved_frac_of_hbm_peak": moved / HBM_PEAK_GBS}
-ROOT = os.path.dirname(os.path.abspath(__file__))
-# rocprofv3 summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE traffic),
-# and the sources whose digest it records.
-PROFILE = os.path.join(ROOT, "profiles", "stage_tile_7_fp64_fmo_batch.md")
-KERNEL_SOURCES = ["paper_1012_4382_amd/csrc/stage_kernels.h",
-                  "paper_1012_4382_amd/csrc/heom_internal.h",
-                  "paper_1012_4382_amd/csrc/kernels_tile_7.hip", "paper_1012_4382_amd/build.py"]
 
 
 def _kernel_digest() -> str:
@@ -60,15 +72,13 @@ def _kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def _profiled_traffic(kernel: str):
+def _profiled_traffic(which: str, kernel: str):
     """Counted HBM bytes per launch from the committed profile, or None when
     the profile is of another kernel or of sources that have changed since."""
     try:
-        text = open(PROFILE).read()
+        text = open(PROFILES[which]).read()
     except OSError:
         return None
-    import re
-
     k = re.search(r"^- kernel: `([^`]+)`", text, re.M)
     d = re.search(r"^- source digest: `([0-9a-f]+)`", text, re.M)
     t = re.search(r"^- traffic per launch \(bytes\): (\d+)", text, re.M)
@@ -82,88 +92,217 @@ def _parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--rk4-steps", type=int, default=5000)
+    p.add_argument("--rk4-steps", type=int, default=1000,
+                   help="RK4 steps of one pass of the sweep (the benchmark step)")
+    p.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                   help="storage precision of the timed sweep")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--no-fmo", action="store_true",
+                   help="skip the FMO-shaped 8-solve batch (depth 7, 5 ps)")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip single-solve, FP32-mixed and one-at-a-time rates and precision")
     p.add_argument("--kernel", default="auto", choices=["auto", "lane", "generic"],
                    help="stage kernel (lane and generic are diagnostic)")
     p.add_argument("--no-sizing", action="store_true",
-                   help="skip the HBM-resident N=7, depth-16 measurement")
+                   help="skip the depth-16 and 24-site sizing launches")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 256 MiB device copy (reference for traffic counters)")
     p.add_argument("--no-batch-scaling", action="store_true",
-                   help="skip the 2-128 solve batches of the benchmarked workload")
-    p.add_argument("--no-sweep", action="store_true",
-                   help="skip the 64-instance parameter-sweep measurement")
-    p.add_argument("--serve", type=int, default=40, metavar="R",
+                   help="skip the 2-128 solve batches of the FMO-shaped workload")
+    p.add_argument("--serve", type=int, default=200, metavar="R",
                    help="serve the first R requests of the serving trace (0: skip)")
-    p.add_argument("--serve-precision", default="fp64", choices=["fp64", "fp32"],
+    p.add_argument("--serve-precision", default="both", choices=["fp64", "fp32", "both"],
                    help="storage precision of the served solves")
     return p.parse_args()
 
 
-def _sweep(heom, torch, workloads, stream):
-    """64 uneven parameter-sweep instances (one Matsubara term per bath, depth
-    3-5), 1000 RK4 steps: one batched launch sequence vs one instance at a time."""
-    ws_ = [workloads.sweep_instance(i) for i in range(64)]
-    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in ws_]
-    r0 = [w["rho0"] for w in ws_]
-    steps = ws_[0]["steps"]
-    total = sum(h.n_ados for h in hs) * steps
-    out = {"instances": len(hs), "ados_min": min(h.n_ados for h in hs),
-           "ados_max": max(h.n_ados for h in hs), "rk4_steps": steps}
-    for prec in ("fp64", "fp32"):
-        ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, prec))
-        heom.propagate_batch(hs, r0, 1.0, 50, record_every=50, precision=prec, workspace=ws,
-                             stream=stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        heom.propagate_batch(hs, r0, 1.0, steps, record_every=steps, precision=prec, workspace=ws,
-                             stream=stream)
-        torch.cuda.synchronize()
-        out[f"{prec}_batched_ado_steps_per_s"] = total / (time.perf_counter() - t0)
-    wsb = heom.allocate_workspace(max(h.workspace_bytes[heom.HEOM_FP64] for h in hs))
+def _load_golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _timed(run, stream, torch, reps, warmup, launches_per_rep):
+    """Times `reps` calls of run() after `warmup` untimed ones: wall clock
+    between two device synchronisations, and HIP events recorded on the
+    library's stream around the same calls.  Returns (seconds, device ms per
+    stage launch, last result)."""
+    out = None
+    for _ in range(warmup):
+        out = run()
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for h, r in zip(hs, r0):
-        heom.propagate(h, r, 1.0, steps, record_every=steps, workspace=wsb, stream=stream)
+    ev0.record(stream)
+    for _ in range(reps):
+        out = run()
+    ev1.record(stream)
     torch.cuda.synchronize()
-    out["fp64_one_at_a_time_ado_steps_per_s"] = total / (time.perf_counter() - t0)
-    out["fp64_batched_over_one_at_a_time"] = (out["fp64_batched_ado_steps_per_s"] /
-                                             out["fp64_one_at_a_time_ado_steps_per_s"])
+    el = time.perf_counter() - t0
+    return el, ev0.elapsed_time(ev1) / (reps * launches_per_rep), out
+
+
+def _roofline(which, kernel, n_ados, N, s, k_ms):
+    """Roofline object of a stage launch over n_ados ADOs that took k_ms."""
+    alg = n_ados * ALG_ADOS_PER_LAUNCH * N * N * s
+    moved = n_ados * MOVED_ADOS_PER_LAUNCH * N * N * s
+    traffic = _profiled_traffic(which, kernel)
+    r = {"bound": "hbm", "achieved": alg / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+         "kernel": kernel, "kernel_avg_us": k_ms * 1e3, "bytes_per_launch": alg,
+         "moved": moved / (k_ms * 1e-3) / 1e9,
+         "moved_frac": moved / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+         "bytes_moved_per_launch": moved}
+    if traffic is not None:
+        r["counted"] = traffic / (k_ms * 1e-3) / 1e9
+        r["counted_frac"] = r["counted"] / HBM_PEAK_GBS
+    return r
+
+
+def _kernel_name(heom, N, KP, n_tiles, precision, kernel):
+    shape, shape_us, streaming, streaming_us = heom.autotune_lookup(N, KP, n_tiles, precision)
+    T = "double" if precision == "fp64" else "float"
+    name = {"auto": (f"stage_tile<{N},{KP},{T},{max(shape, 0)}>" if shape != 5
+                     else f"stage_wide<{T},{KP}>")
+                    + (" with streaming stores" if streaming == 1 else ""),
+            "lane": f"stage_fixed<{N},{KP},{T}>",
+            "generic": f"stage_generic<{T}>"}[kernel]
+    tune = {"tiles": n_tiles, "shape": shape, "streaming_stores": streaming,
+            "stage_us_per_shape": [round(float(u), 3) for u in shape_us],
+            "stage_us_streaming": round(float(streaming_us), 3),
+            "shapes": [heom.tile_shape_info(N, KP, precision, k)
+                       for k in range(heom.tile_shape_count())]}
+    return name, tune
+
+
+def _check_sweep(rhos, sinks, golden, prec):
+    """The timed sweep's instances against the oracle's stored trajectories:
+    max relative deviation of sigma_0 (every 100 steps) and of P_trap."""
+    if golden is None:
+        return None
+    idx = [int(i) for i in golden["instances"]]
+    drho = max(float(np.max(np.abs(rhos[i] - golden["rho"][k])) / np.max(np.abs(golden["rho"][k])))
+               for k, i in enumerate(idx))
+    dtrap = max(abs(float(sinks[i][0]) - float(golden["scalars"][k][0])) /
+                abs(float(golden["scalars"][k][0])) for k, i in enumerate(idx))
+    return {"instances_checked": len(idx), "max_rel_rho_error": drho,
+            "max_rel_p_trap_error": dtrap, "bar": 1e-10 if prec == "fp64" else 1e-5}
+
+
+def _fmo_batch(heom, torch, workloads, stream, args):
+    """The FMO-shaped 7-site workload at depth 7 (3432 ADOs per solve), all 8
+    solves (seeds 0-3, start at site 1 or 6), 5000 RK4 steps (5 ps), sigma_0
+    every 10 steps, FP64: timed like the headline, its roofline, and its
+    timed runs against the oracle's trajectories (populations every 10 steps,
+    sigma_0 every 100, eta at 5 ps)."""
+    batch = workloads.fmo_like_batch(steps=5000)
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in batch]
+    r0 = [w["rho0"] for w in batch]
+    N = hs[0].N
+    total = sum(h.n_ados for h in hs)
+    ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, "fp64"))
+
+    def run():
+        return heom.propagate_batch(hs, r0, 1.0, 5000, record_every=10, workspace=ws,
+                                    stream=stream, kernel=args.kernel)
+
+    reps = max(2, args.steps // 4)
+    el, k_ms, (rhos, sinks, _) = _timed(run, stream, torch, reps, 1, 4 * 5000)
+    name, tune = _kernel_name(heom, N, 1, sum((h.n_ados + 63) // 64 for h in hs), "fp64",
+                              args.kernel)
+    out = {"workload": "fmo_like_7site_depth7_fp64_8solves_5ps", "n_ados": total,
+           "passes": reps, "ado_steps_per_s": total * 5000 * reps / el,
+           "ms_per_pass": 1e3 * el / reps, "roofline": _roofline("fmo", name, total, N, 8, k_ms),
+           "autotune": tune}
+    g = _load_golden("oracle_fmo_like_depth7.npz")
+    if g is not None:
+        pops = [np.real(np.diagonal(r, axis1=1, axis2=2)) for r in rhos]
+        out["check_vs_oracle"] = {
+            "solves": len(hs),
+            "max_rel_pop_error": max(float(np.max(np.abs(p - g["pops"][k])) /
+                                           np.max(np.abs(g["pops"][k])))
+                                     for k, p in enumerate(pops)),
+            "max_rel_rho_error": max(float(np.max(np.abs(r[::10] - g["rho"][k])) /
+                                           np.max(np.abs(g["rho"][k])))
+                                     for k, r in enumerate(rhos)),
+            "max_rel_eta_error": max(abs(float(sinks[k][0]) - float(g["scalars"][k][0])) /
+                                     float(g["scalars"][k][0]) for k in range(len(hs))),
+            "eta_5ps": [float(s[0]) for s in sinks], "bar": 1e-10}
+    if not args.no_variants:
+        # Plain single solve (FP64 and FP32-mixed) and the FP32-mixed batch.
+        def single(prec):
+            w1 = heom.allocate_workspace(hs[0].workspace_bytes[heom.PRECISIONS[prec]])
+            heom.propagate(hs[0], r0[0], 1.0, 64, record_every=64, workspace=w1, stream=stream,
+                           precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            heom.propagate(hs[0], r0[0], 1.0, 5000, record_every=10, workspace=w1,
+                           stream=stream, precision=prec)
+            torch.cuda.synchronize()
+            return hs[0].n_ados * 5000 / (time.perf_counter() - t0)
+
+        ws32 = heom.allocate_workspace(heom.batch_workspace_bytes(hs, "fp32"))
+        el32, _, _ = _timed(lambda: heom.propagate_batch(hs, r0, 1.0, 5000, record_every=10,
+                                                         precision="fp32", workspace=ws32,
+                                                         stream=stream), stream, torch, 1, 1, 1)
+        p64, p32 = single("fp64"), single("fp32")
+        out["variants"] = {"fp64_single_solve_ado_steps_per_s": p64,
+                           "fp32_single_solve_ado_steps_per_s": p32,
+                           "fp32_mixed_batched_ado_steps_per_s": total * 5000 / el32,
+                           "fp64_batched_over_single": out["ado_steps_per_s"] / p64,
+                           "fp32_batched_over_single": total * 5000 / el32 / p32}
+    for h in hs:
+        h.close()
     return out
 
 
 def _precision(heom, workloads, stream):
     """Precision workload: depth 8 (6435 ADOs), seeds 0-1, T = 77 and 300 K,
-    excitation at site 1, 5 ps.  Reports the FP32-mixed path's deviation from
-    the FP64 path (itself checked against the FP64 oracle to 1e-10 by the
-    tests): max |dp| over all populations and steps, and |d eta|."""
-    cases = [workloads.fmo_like(seed=s, site=1, depth=8, T=T) for s in (0, 1) for T in (77.0, 300.0)]
+    excitation at site 1, 5 ps, FP32-mixed and FP64, against the FP64
+    oracle's trajectories: max |dp| over all populations every 10 steps, and
+    |d eta| at 5 ps."""
+    g = _load_golden("oracle_precision_depth8.npz")
+    if g is None:
+        return None
+    cases = [workloads.fmo_like(seed=int(s), site=1, depth=8, T=float(T))
+             for s, T in zip(g["seeds"], g["temperatures"])]
     hs = [heom.Hierarchy(w["system"], w["depth"]) for w in cases]
     r0 = [w["rho0"] for w in cases]
-    steps = cases[0]["steps"]
-    res = {}
-    for prec in ("fp64", "fp32"):
-        rhos, sinks, _ = heom.propagate_batch(hs, r0, 1.0, steps, record_every=10, precision=prec,
+    out = {"workload": "fmo_like_7site_depth8_T77_300_seeds01_5ps", "n_ados": hs[0].n_ados,
+           "reference": "FP64 oracle (tests/golden/oracle_precision_depth8.npz)"}
+    for prec in ("fp32", "fp64"):
+        rhos, sinks, _ = heom.propagate_batch(hs, r0, 1.0, 5000, record_every=10, precision=prec,
                                               stream=stream)
-        res[prec] = (rhos, sinks)
-    dp = max(float(np.max(np.abs(np.real(np.diagonal(a, axis1=1, axis2=2)) -
-                                 np.real(np.diagonal(b, axis1=1, axis2=2)))))
-             for a, b in zip(res["fp32"][0], res["fp64"][0]))
-    ptrap = res["fp64"][1][:, 0]
-    dtrap = np.abs(res["fp32"][1][:, 0] - ptrap)
-    return {"workload": "fmo_like_7site_depth8_T77_300_seeds01_5ps", "n_ados": hs[0].n_ados,
-            "max_abs_pop_error": dp, "max_abs_p_trap_error": float(np.max(dtrap)),
-            "max_rel_p_trap_error": float(np.max(dtrap / ptrap)), "bar": 1e-5}
+        dp = max(float(np.max(np.abs(np.real(np.diagonal(r, axis1=1, axis2=2)) - g["pops"][k])))
+                 for k, r in enumerate(rhos))
+        de = max(abs(float(sinks[k][0]) - float(g["scalars"][k][0])) for k in range(len(hs)))
+        out[prec] = {"max_abs_pop_error": dp, "max_abs_eta_error": de,
+                     "max_rel_eta_error": max(abs(float(sinks[k][0]) - float(g["scalars"][k][0])) /
+                                              float(g["scalars"][k][0]) for k in range(len(hs))),
+                     "bar": 1e-5 if prec == "fp32" else 1e-10}
+    for h in hs:
+        h.close()
+    return out
 
 
-def _serve(heom, workloads, stream, n_requests, precision="fp64"):
+def _alg_bytes(r):
+    N = r.system["H"].shape[0]
+    return comb(N + r.depth, r.depth) * r.steps * 128.0 * N * N
+
+
+def _serve(heom, workloads, stream, n_requests, precision):
     """The first n_requests of the serving trace (Poisson arrivals, mean 50 ms;
     N in {2,7,8,12,24}, depth 2-4, 2-10 ps), served by the continuous-batching
-    engine in real time, then the same requests one at a time (FIFO).  A sample
-    of the served results is checked against the same solves run alone in
-    FP64 (bitwise for FP64 serving, within 1e-5 for FP32-mixed)."""
+    engine in real time, then the same requests one at a time (FIFO).  Every
+    served result is compared with the same request served alone (bitwise)
+    and with the FP64 oracle's stored result where that covers the whole run
+    (FP64 1e-10 relative, FP32-mixed 1e-5 absolute on populations and eta).
+    Utilisation: the offered load (algorithmic bytes of the trace per second
+    of its arrival span) over the engine's measured capacity (bytes per
+    second of makespan while saturated); the highest sustainable arrival
+    rate is the capacity over the mean bytes of a request."""
     from paper_1012_4382_amd.serve import Engine, GpuBackend, Request
 
     def reqs():
@@ -176,7 +315,7 @@ def _serve(heom, workloads, stream, n_requests, precision="fp64"):
 
         def on_finish(r):
             count[0] += 1
-            if count[0] % 10 == 0 or count[0] == n_requests:
+            if count[0] % 20 == 0 or count[0] == n_requests:
                 print(f"serve {tag} {precision}: {count[0]}/{n_requests} finished",
                       file=sys.stderr, flush=True)
         return on_finish
@@ -189,24 +328,47 @@ def _serve(heom, workloads, stream, n_requests, precision="fp64"):
     m = eng.run(served, on_finish=progress("batched"))
     fifo = Engine(GpuBackend(stream=stream), hbm_budget_bytes=budget, chunk_steps=200,
                   max_active=1)
-    mf = fifo.run(reqs(), on_finish=progress("fifo"))
-    # Check: up to 8 served solves (of at most 2e7 ADO-steps each) against the
-    # same solve alone in FP64.
-    sample = [r for r in served if r.status == "done" and r.n_ados * r.steps <= 2e7][:8]
-    dp, dtrap, bitwise = 0.0, 0.0, True
-    for r in sample:
-        h = heom.Hierarchy(r.system, r.depth)
-        rho, sinks, _ = heom.propagate(h, r.rho0, r.dt, r.steps, record_every=r.steps,
-                                       stream=stream)
-        ref = rho[-1]
-        dp = max(dp, float(np.max(np.abs(np.real(np.diag(r.rho_final)) - np.real(np.diag(ref))))))
-        dtrap = max(dtrap, abs(float(r.sinks[0]) - float(sinks[0])))
-        bitwise = bitwise and np.array_equal(r.rho_final, ref) and np.array_equal(r.sinks, sinks)
-    return {"requests": n_requests, "precision": precision, "budget_bytes": budget,
-            "continuous_batching": m, "fifo_one_at_a_time": mf,
-            "check_vs_fp64_alone": {"sample": [r.id for r in sample],
-                                    "max_abs_pop_error": dp, "max_abs_p_trap_error": dtrap,
-                                    "bitwise_equal": bool(bitwise), "bar": 1e-5}}
+    alone = reqs()
+    mf = fifo.run(alone, on_finish=progress("fifo"))
+    total_bytes = sum(_alg_bytes(r) for r in served)
+    span = max(r.arrival_s for r in served)
+    capacity = total_bytes / m["makespan_s"]
+    offered = total_bytes / span
+    # Served against alone (bitwise: the same arithmetic), every request.
+    by_id = {r.id: r for r in alone}
+    bitwise = all(r.status == "done" and np.array_equal(r.rho_final, by_id[r.id].rho_final) and
+                  np.array_equal(r.sinks, by_id[r.id].sinks) for r in served)
+    out = {"requests": n_requests, "precision": precision, "budget_bytes": budget,
+           "continuous_batching": m, "fifo_one_at_a_time": mf,
+           "batched_over_fifo_ado_steps_per_s": m["ado_steps_per_s"] / mf["ado_steps_per_s"],
+           "offered_alg_bytes_per_s": offered, "capacity_alg_bytes_per_s": capacity,
+           "utilisation": offered / capacity,
+           "arrival_rate_per_s": n_requests / span,
+           "highest_sustainable_arrival_rate_per_s": capacity / (total_bytes / n_requests),
+           "served_equal_alone_bitwise": {"requests": len(served), "all_equal": bool(bitwise),
+                                          "n_sites_24": sum(r.system["H"].shape[0] == 24
+                                                            for r in served)}}
+    g = _load_golden("oracle_serving.npz")
+    if g is not None:
+        full, dp, dt_, rel = 0, 0.0, 0.0, 0.0
+        for r in served:
+            j = r.id
+            if j >= len(g["done"]) or not g["done"][j] or int(g["steps"][j]) != r.steps:
+                continue
+            N = r.system["H"].shape[0]
+            ref = g["rho_flat"][g["rho_off"][j]:g["rho_off"][j + 1]].reshape(N, N)
+            full += 1
+            dp = max(dp, float(np.max(np.abs(np.real(np.diag(r.rho_final)) -
+                                             np.real(np.diag(ref))))))
+            dt_ = max(dt_, abs(float(r.sinks[0]) - float(g["scalars"][j][0])))
+            rel = max(rel, float(np.max(np.abs(r.rho_final - ref)) / np.max(np.abs(ref))))
+        partial = int(np.sum(g["done"][:n_requests])) - full
+        out["check_vs_oracle"] = {
+            "requests_full_length": full, "max_abs_pop_error": dp, "max_abs_eta_error": dt_,
+            "max_rel_rho_error": rel,
+            "requests_checked_over_first_steps_in_tests": partial,
+            "bar": 1e-10 if precision == "fp64" else 1e-5}
+    return out
 
 
 def _stage_kernel_timing(heom, torch, hs, rho0s, stream, kernel, precision="fp64", steps=500):
@@ -260,8 +422,8 @@ def _wide_sizing(heom, torch, workloads, stream, kernel):
     return out
 
 
-def _batch_scaling(heom, torch, workloads, stream, kernel, sizes=(2, 4, 16, 32, 64, 128)):
-    """The benchmarked workload with more solves per launch sequence (seeds
+def _batch_scaling(heom, torch, workloads, stream, kernel, sizes=(2, 4, 8, 16, 32, 64, 128)):
+    """The FMO-shaped workload with more solves per launch sequence (seeds
     0..n/2-1, sites 1 and 6): where the stage kernel leaves the latency-bound
     regime of a few hundred tiles.  Beside it, a plain 1 GiB device copy, the
     bandwidth a kernel that only streams can reach on this GPU."""
@@ -297,24 +459,56 @@ def _batch_scaling(heom, torch, workloads, stream, kernel, sizes=(2, 4, 16, 32, 
             "device_copy_frac_of_hbm_peak": copy_gbs / HBM_PEAK_GBS}
 
 
-def _cpu_baseline(w, target_s=12.0):
-    """The oracle (as it stands) on this host, on a bounded sample of one solve."""
+def _cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        m = re.search(r"^Model name:\s*(.+)$", out, re.M)
+        if m:
+            return m.group(1).strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(target_s=12.0):
+    """The oracle (as it stands) on this host, on a bounded sample of the
+    benchmark's workload: sweep instance 2 (depth 5, 11628 ADOs, the largest
+    shape of the sweep) for as many of its 1000 RK4 steps as fit in about
+    target_s seconds, on every host thread and then on one thread."""
     import oracle
+    from paper_1012_4382_amd import workloads
 
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    w = workloads.sweep_instance(2)
     n_ado = oracle.count(w["system"], w["depth"])[0]
-    t0 = time.perf_counter()
-    oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], 10, record_every=10,
-                     n_threads=cores)
-    per_step = (time.perf_counter() - t0) / 10
-    steps = max(10, int(target_s / per_step))
-    t0 = time.perf_counter()
-    oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], steps, record_every=steps,
-                     n_threads=cores)
-    el = time.perf_counter() - t0
-    return {"value": n_ado * steps / el, "unit": "ADO-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"one solve of the benchmarked workload (seed 0, site 1, {n_ado} ADOs), "
-                      f"first {steps} of its 5000 RK4 steps, {el:.1f} s, {cores} OpenMP threads"}
+    out = {"unit": "ADO-steps/s", "kind": "oracle", "cpu_model": _cpu_model()}
+    for threads in (cores, 1):
+        t0 = time.perf_counter()
+        oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], 2, record_every=2,
+                         n_threads=threads)
+        per_step = (time.perf_counter() - t0) / 2
+        steps = int(max(2, min(w["steps"], target_s / per_step)))
+        t0 = time.perf_counter()
+        oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], steps, record_every=steps,
+                         n_threads=threads)
+        el = time.perf_counter() - t0
+        rate = n_ado * steps / el
+        if threads == cores:
+            out.update(value=rate, cores=cores,
+                       sample=f"sweep instance 2 of the benchmark (N=7, one Matsubara term per "
+                              f"bath, depth {w['depth']}, {n_ado} ADOs), first {steps} of its "
+                              f"{w['steps']} RK4 steps, {el:.1f} s on {cores} OpenMP threads")
+        else:
+            out["one_thread"] = {"value": rate, "cores": 1,
+                                 "sample": f"the same instance, first {steps} steps, {el:.1f} s "
+                                           f"on 1 thread"}
+    return out
 
 
 def main():
@@ -331,57 +525,37 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
+    prec = args.precision
     steps_rk = args.rk4_steps
-    batch = workloads.fmo_like_batch(steps=steps_rk)
-    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in batch]
-    rho0s = [w["rho0"] for w in batch]
-    n_ados = hs[0].n_ados
-    N = hs[0].N
+    record_every = 100
+    cases = [workloads.sweep_instance(i) for i in range(64)]
+    hs = [heom.Hierarchy(w["system"], w["depth"]) for w in cases]
+    rho0s = [w["rho0"] for w in cases]
+    N, KP = hs[0].N, hs[0].n_modes // hs[0].N
     total_ados = sum(h.n_ados for h in hs)
-    ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, "fp64"))
-    record_every = 10
+    ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, prec))
 
-    def one_pass(precision="fp64", workspace=ws, hh=hs, r0=rho0s):
-        return heom.propagate_batch(hh, r0, 1.0, steps_rk, record_every=record_every,
-                                    precision=precision, workspace=workspace, stream=stream,
+    def one_pass():
+        return heom.propagate_batch(hs, rho0s, 1.0, steps_rk, record_every=record_every,
+                                    precision=prec, workspace=ws, stream=stream,
                                     kernel=args.kernel)
 
-    for _ in range(args.warmup):
-        one_pass()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rhos, sinks, _ = one_pass()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ado_steps = total_ados * steps_rk * args.steps
-    value = ado_steps / el
+    print(f"bench: sweep of 64 instances ({total_ados} ADOs), {steps_rk} RK4 steps, {prec}: "
+          f"{args.warmup} warm-up and {args.steps} timed passes", file=sys.stderr, flush=True)
+    el, kernel_ms, (rhos, sinks, _) = _timed(one_pass, stream, torch, args.steps, args.warmup,
+                                             4 * steps_rk)
+    value = total_ados * steps_rk * args.steps / el
     ms_per_step = 1e3 * el / args.steps
     # Population conservation of the timed runs (exact for RK4): Tr rho + P_trap + P_rec = 1.
     defect = max(abs(np.trace(r[-1]).real + s[0] + s[1] - 1.0) for r, s in zip(rhos, sinks))
-
-    # Dominant kernel: the fused RK4 stage.  Average duration per launch from
-    # HIP events on the library's stream over a run without history records.
-    kernel_ms, _ = _stage_kernel_timing(heom, torch, hs, rho0s, stream, args.kernel)
-    # Algorithmic bytes per launch (4 packed ADOs per ADO, the classic RK4
-    # figure) and the bytes the nested form moves (11/4 per ADO).
-    bytes_per_launch = total_ados * ALG_ADOS_PER_LAUNCH * N * N * 8
-    bytes_moved = total_ados * MOVED_ADOS_PER_LAUNCH * N * N * 8
-    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    moved = bytes_moved / (kernel_ms * 1e-3) / 1e9
-    # Launch shape the autotuner chose for this workload (during the warm-up).
     n_tiles = sum((h.n_ados + 63) // 64 for h in hs)
-    shape, shape_us, streaming, streaming_us = heom.autotune_lookup(N, 1, n_tiles, "fp64")
-    kernel_name = {"auto": f"stage_tile<{N},1,double,{max(shape, 0)}>"
-                           + (" with streaming stores" if streaming == 1 else ""),
-                   "lane": f"stage_fixed<{N},1,double>",
-                   "generic": "stage_generic<double>"}[args.kernel]
-    autotune = {"tiles": n_tiles, "shape": shape, "streaming_stores": streaming,
-                "stage_us_per_shape": [round(float(u), 3) for u in shape_us],
-                "stage_us_streaming": round(float(streaming_us), 3),
-                "shapes": [heom.tile_shape_info(N, 1, "fp64", k)
-                           for k in range(heom.tile_shape_count())]}
-
+    kernel_name, autotune = _kernel_name(heom, N, KP, n_tiles, prec, args.kernel)
+    s_bytes = 8 if prec == "fp64" else 4
+    roof = _roofline("sweep", kernel_name, total_ados, N, s_bytes, kernel_ms)
+    roof["kernel_avg_us_note"] = ("device time of the timed passes per stage launch (HIP events "
+                                  "on the library's stream), an upper bound of the kernel's "
+                                  "average duration: it includes the gaps between launches "
+                                  "and the sigma_0 snapshot kernels")
     result = {
         "metric": "HEOM ADO-steps/s (FP64, FP32) vs plain; serving p50/p99 latency at ≤1e-5 error",
         "value": value,
@@ -393,64 +567,53 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "fmo_like_7site_depth7_fp64_8solves_5ps", "n_sites": 7,
-                   "depth": 7, "n_ados_per_solve": n_ados, "solves": len(hs),
+        "config": {"workload": f"sweep_64x_fmo_like_7site_k1_depth3to5_{prec}_1000steps",
+                   "instances": len(hs), "n_sites": N, "matsubara_per_bath": KP - 1,
+                   "depths": [h.depth for h in hs], "n_ados_total": total_ados,
                    "rk4_steps": steps_rk, "dt_fs": 1.0, "record_every": record_every,
                    "parallelism": "single_gpu"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": _profiled_traffic(kernel_name),
-                     "kernel": kernel_name,
-                     "kernel_avg_us": kernel_ms * 1e3, "bytes_per_launch": bytes_per_launch,
-                     "moved": moved, "moved_frac": moved / HBM_PEAK_GBS,
-                     "bytes_moved_per_launch": bytes_moved},
+        "roofline": roof,
         "population_defect": defect,
+        "timed_run_check": _check_sweep(rhos, sinks, _load_golden("oracle_sweep_k1.npz"), prec),
         "autotune": autotune,
     }
     if not args.no_variants:
-        # Plain single solve (one instance at a time, FP64 and FP32-mixed, each
-        # after a short warm-up call) and the FP32-mixed batch.
-        ws1 = heom.allocate_workspace(hs[0].workspace_bytes[heom.HEOM_FP64])
-        heom.propagate(hs[0], rho0s[0], 1.0, 64, record_every=64, workspace=ws1, stream=stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        heom.propagate(hs[0], rho0s[0], 1.0, steps_rk, record_every=record_every, workspace=ws1,
-                       stream=stream)
-        torch.cuda.synchronize()
-        plain = n_ados * steps_rk / (time.perf_counter() - t0)
-        ws32 = heom.allocate_workspace(heom.batch_workspace_bytes(hs, "fp32"))
-        one_pass("fp32", ws32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        one_pass("fp32", ws32)
-        torch.cuda.synchronize()
-        fp32 = total_ados * steps_rk / (time.perf_counter() - t0)
-        ws1f = heom.allocate_workspace(hs[0].workspace_bytes[heom.HEOM_FP32_MIXED])
-        heom.propagate(hs[0], rho0s[0], 1.0, 64, record_every=64, workspace=ws1f, stream=stream,
-                       precision="fp32")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        heom.propagate(hs[0], rho0s[0], 1.0, steps_rk, record_every=record_every, workspace=ws1f,
-                       stream=stream, precision="fp32")
-        torch.cuda.synchronize()
-        plain32 = n_ados * steps_rk / (time.perf_counter() - t0)
-        result["variants"] = {"fp64_single_solve_ado_steps_per_s": plain,
-                              "fp32_single_solve_ado_steps_per_s": plain32,
-                              "fp32_batched_over_single": fp32 / plain32,
-                              "fp32_mixed_batched_ado_steps_per_s": fp32,
-                              "fp64_batched_over_single": value / plain}
+        # The same sweep in the other precision and one instance at a time.
+        other = "fp32" if prec == "fp64" else "fp64"
+        ws_o = heom.allocate_workspace(heom.batch_workspace_bytes(hs, other))
+        el_o, k_o, (rh_o, sk_o, _) = _timed(
+            lambda: heom.propagate_batch(hs, rho0s, 1.0, steps_rk, record_every=record_every,
+                                         precision=other, workspace=ws_o, stream=stream),
+            stream, torch, 2, 1, 4 * steps_rk)
+        wsb = heom.allocate_workspace(max(h.workspace_bytes[heom.PRECISIONS[prec]] for h in hs))
+
+        def one_at_a_time():
+            for h, r in zip(hs, rho0s):
+                heom.propagate(h, r, 1.0, steps_rk, record_every=steps_rk, workspace=wsb,
+                               stream=stream, precision=prec)
+
+        el_1, _, _ = _timed(one_at_a_time, stream, torch, 1, 0, 1)
+        result["sweep_variants"] = {
+            f"{other}_batched_ado_steps_per_s": total_ados * steps_rk * 2 / el_o,
+            f"{other}_kernel_avg_us": k_o * 1e3,
+            f"{other}_timed_run_check": _check_sweep(rh_o, sk_o,
+                                                     _load_golden("oracle_sweep_k1.npz"), other),
+            f"{prec}_one_at_a_time_ado_steps_per_s": total_ados * steps_rk / el_1,
+            f"{prec}_batched_over_one_at_a_time": value / (total_ados * steps_rk / el_1)}
+    if not args.no_fmo:
+        result["fmo_batch"] = _fmo_batch(heom, torch, workloads, stream, args)
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
         result["wide_sizing"] = _wide_sizing(heom, torch, workloads, stream, args.kernel)
     if not args.no_batch_scaling:
         result["batch_scaling"] = _batch_scaling(heom, torch, workloads, stream, args.kernel)
-    if not args.no_sweep:
-        result["sweep"] = _sweep(heom, torch, workloads, stream)
     if not args.no_variants:
         result["precision"] = _precision(heom, workloads, stream)
     if args.serve > 0:
-        result["serving"] = _serve(heom, workloads, stream, args.serve, args.serve_precision)
+        precs = ("fp64", "fp32") if args.serve_precision == "both" else (args.serve_precision,)
+        result["serving"] = {p: _serve(heom, workloads, stream, args.serve, p) for p in precs}
     if args.copy_calibration:
         # A plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
         # kernel calibrate the traffic counters of the stage kernel.
@@ -461,7 +624,7 @@ def main():
         torch.cuda.synchronize()
         result["copy_calibration_bytes"] = src.numel() * 8
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = _cpu_baseline(batch[0])
+        result["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(result), flush=True)
 
 

@@ -198,7 +198,11 @@ int heom_slots_scratch_bytes(heom_hierarchy *const *hs, int32_t n, size_t *bytes
  * Each run's arithmetic does not depend on the others: its results equal
  * those of heom_propagate on that run alone.  A workspace advanced here can be
  * continued by heom_propagate with HEOM_RESUME and vice versa.
- * Errors as heom_propagate. */
+ * Errors as heom_propagate, except HEOM_E_NUMERIC: it means that every slot
+ * was advanced by n_steps and rho_out / sinks_out were written for all of
+ * them, and that the slots whose outputs hold a NaN or Inf (listed in
+ * heom_last_error) are the failed ones; the other slots are valid and may be
+ * continued.  After any other error the state of every slot is undefined. */
 int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
                        void *const *d_workspaces, const size_t *workspace_bytes,
                        const int32_t *start, const double *const *rho0s, double dt_fs,

@@ -47,10 +47,20 @@ _FIRST = ["kernels_tile_12.hip", "kernels_tile_11.hip", "kernels_tile_9_10.hip",
           "kernels_tile_8.hip", "kernels_tile_small.hip", "kernels_tile_7.hip"]
 
 
-def _compile(unit, defines=(), build_dir: str = BUILD_DIR) -> str:
+def _newest_input(src: str) -> float:
+    """Modification time of a source and of every header it can include."""
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    heads += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    return max(os.path.getmtime(p) for p in [os.path.join(CSRC, src), __file__, *heads])
+
+
+def _compile(unit, defines=(), build_dir: str = BUILD_DIR, incremental: bool = False) -> str:
     src, shape, f64 = unit
     stem = os.path.basename(src) + ("" if shape is None else f".s{shape}.f{int(f64)}")
     obj = os.path.join(build_dir, stem + ".o")
+    if (incremental and not defines and os.path.exists(obj) and
+            os.path.getmtime(obj) > _newest_input(src)):
+        return obj
     lang = ["-x", "hip"] if src.endswith(".hip") else []
     extra = [] if shape is None else [f"-DHEOM_SHAPE={shape}", f"-DHEOM_TILE_F64={int(f64)}"]
     if f64:
@@ -63,8 +73,11 @@ def _compile(unit, defines=(), build_dir: str = BUILD_DIR) -> str:
     return obj
 
 
-def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD_DIR) -> str:
-    """Compiles every source and links libheom.so (or `out`); always rebuilds.
+def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD_DIR,
+          incremental: bool = False) -> str:
+    """Compiles every source and links libheom.so (or `out`); rebuilds every
+    object unless `incremental` (then only objects older than their source, a
+    header or this script).
 
     `defines` are extra preprocessor definitions (tuning knobs of the kernels).
     """
@@ -72,7 +85,7 @@ def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BU
     order = sorted(SOURCES, key=lambda u: _FIRST.index(u[0]) if u[0] in _FIRST else len(_FIRST))
     workers = max(1, min(len(order), os.cpu_count() or 1, 16))
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        objs = list(ex.map(lambda src: _compile(src, defines, build_dir), order))
+        objs = list(ex.map(lambda src: _compile(src, defines, build_dir, incremental), order))
     tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -85,5 +98,5 @@ def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BU
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

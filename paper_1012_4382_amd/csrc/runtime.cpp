@@ -136,13 +136,20 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   return L;
 }
 
-int ensure_device_tables(const heom_hierarchy *h, int device, heom_hierarchy::DeviceTables *out) {
+// The device copy of h's neighbour tables on `device`, uploaded on first use
+// (with upload = false a missing copy is an error: nothing is allocated).
+int ensure_device_tables(const heom_hierarchy *h, int device, heom_hierarchy::DeviceTables *out,
+                         bool upload = true) {
   std::lock_guard<std::mutex> lock(h->mu);
   for (const auto &t : h->dev)
     if (t.device == device) {
       *out = t;
       return HEOM_OK;
     }
+  if (!upload)
+    return fail(HEOM_E_UNSUPPORTED,
+                "the neighbour tables of a hierarchy are not on this device yet (an allocating "
+                "call with that hierarchy on this device uploads them)");
   heom_hierarchy::DeviceTables t;
   t.device = device;
   const size_t n32 = h->up.size() * sizeof(int32_t);
@@ -404,10 +411,22 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
 
 // Propagates n instances placed as described by `place`.  start[k] = 1
 // initialises instance k from rho0s[k]; 0 continues the run held there.
+// How run_impl runs.
+struct RunOptions {
+  // Fail with HEOM_E_NUMERIC at the first non-finite record (otherwise the
+  // records are returned as they are and the caller checks them).
+  bool check_numeric = true;
+  // Allocate nothing on the device (and create no stream, event or graph):
+  // tables must already be resident, launch shapes come from the autotuner's
+  // cache or the defaults, every launch goes directly to the caller's stream.
+  bool no_alloc = false;
+};
+
 int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const int32_t *start,
              const double *const *rho0s, double dt_fs, int64_t n_steps, int64_t record_every,
              const RunPlace &place, void *hip_stream, double *const *rho_outs,
-             double *const *sinks_outs) {
+             double *const *sinks_outs, const RunOptions &opt = RunOptions()) {
+  const bool check_numeric = opt.check_numeric;
   const bool mixed = precision == HEOM_FP32_MIXED;
   // Packed initial states (validated before any device work).
   std::vector<std::vector<double>> params(n);
@@ -438,7 +457,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   std::vector<InstDesc> descs(n);
   for (int k = 0; k < n; ++k) {
     heom_hierarchy::DeviceTables t;
-    int rc = ensure_device_tables(hs[k], device, &t);
+    int rc = ensure_device_tables(hs[k], device, &t, !opt.no_alloc);
     if (rc) return rc;
     char *ws = place.base[k];
     const InstLayout &I = place.inst[k];
@@ -599,7 +618,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       const size_t rec_len = static_cast<size_t>(N) * N + kScalars;
       for (int s = 0; s < slot; ++s) {
         const double *src = host_ring[k].data() + rec_len * s;
-        for (size_t q = 0; q < rec_len - 1; ++q)
+        for (size_t q = 0; check_numeric && q < rec_len - 1; ++q)
           if (!std::isfinite(src[q]))
             return fail(HEOM_E_NUMERIC, "non-finite reduced density matrix at record " +
                                             std::to_string(rec_done + s));
@@ -628,6 +647,16 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     int shape = forced_shape(flags);  // validated by check_common
     bool streaming = false;
     if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = g.shape;
+    if (shape < 0 && opt.no_alloc) {
+      // No timing runs (they create events): the tuned configuration if this
+      // process has one for the key, else the default shape.
+      int s = -1, nt = -1;
+      int rc = autotune_lookup(device, mixed, g.N, g.KP, g.n_tiles, &s, &nt, nullptr, nullptr);
+      if (rc) return rc;
+      const bool ok = s >= 0 && s < kMaxTileShapes && g.count[g.list(s)] > 0;
+      shape = ok ? s : g.shape;
+      streaming = ok && nt == 1;
+    }
     if (shape < 0) {
       auto time_shape = [&](int s, bool nt, double *us) -> int {
         if (nt && !has_streaming_stores(g.N, g.KP, mixed, s)) {
@@ -679,7 +708,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   // stream, and `s` waits for all of them before the next stage.  (In a
   // graph capture this gives parallel branches.)
   ForkJoin *fj = nullptr;
-  if (groups.size() > 1) {
+  if (groups.size() > 1 && !opt.no_alloc) {
     int rc = fork_join(device, groups.size(), &fj);
     if (rc) return rc;
   }
@@ -714,7 +743,8 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   // Runs of kGraphSteps steps are replayed from one captured graph, which
   // removes the host launch cost of each stage kernel.
   StepGraph graph;
-  const bool use_graph = (flags & HEOM_NO_GRAPH) == 0 && n_steps >= kGraphSteps;
+  const bool use_graph =
+      (flags & HEOM_NO_GRAPH) == 0 && n_steps >= kGraphSteps && !opt.no_alloc;
   if (use_graph) {
     int rc = graph.build(device, kGraphSteps, enqueue_step);
     if (rc) return rc;
@@ -808,6 +838,83 @@ SlotScratch slot_scratch(heom_hierarchy *const *hs, int n) {
   s.work = off;
   s.total = align_up(off + sizeof(WorkItem) * s.work_cap);
   return s;
+}
+
+// heom_advance_slots and its allocation-free variant (no_alloc: the scratch
+// is the library's static device array, nothing is allocated or created).
+int advance_slots_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
+                       void *const *d_workspaces, const size_t *workspace_bytes,
+                       const int32_t *start, const double *const *rho0s, double dt_fs,
+                       int64_t n_steps, void *d_scratch, size_t scratch_bytes, void *hip_stream,
+                       double *const *rho_out, double *const *sinks_out, bool no_alloc) {
+  int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, 1,
+                        HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
+                            HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
+                            kShapeFlagMask);
+  if (rc) return rc;
+  if (!d_workspaces || !workspace_bytes || !start)
+    return fail(HEOM_E_INVALID, "workspaces, sizes and start flags are required");
+  const SlotScratch sc = slot_scratch(hs, n);
+  if (no_alloc && sc.total > scratch_bytes)
+    return fail(HEOM_E_WORKSPACE, "these slots need " + std::to_string(sc.total) +
+                                      " bytes of launch scratch; the static scratch holds " +
+                                      std::to_string(scratch_bytes));
+  if (!d_scratch || reinterpret_cast<uintptr_t>(d_scratch) % kAlign || scratch_bytes < sc.total)
+    return fail(HEOM_E_WORKSPACE, "scratch missing, misaligned or too small: need " +
+                                      std::to_string(sc.total) + " bytes");
+  RunPlace P;
+  for (int k = 0; k < n; ++k) {
+    heom_hierarchy *h = hs[k];
+    const Layout L1 = make_layout(&h, 1, precision);
+    char *ws = static_cast<char *>(d_workspaces[k]);
+    if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign || workspace_bytes[k] < L1.total)
+      return fail(HEOM_E_WORKSPACE, "workspace " + std::to_string(k) +
+                                        " missing, misaligned or too small");
+    for (int j = 0; j < k; ++j)
+      if (d_workspaces[j] == d_workspaces[k])
+        return fail(HEOM_E_INVALID, "two slots share one workspace");
+    P.base.push_back(ws);
+    P.inst.push_back(L1.inst[0]);
+    P.header.push_back(ws + L1.header);
+    P.want.push_back(header_for(&h, 1, precision));
+    P.header_of.push_back(k);
+  }
+  char *s = static_cast<char *>(d_scratch);
+  P.descs = s + sc.descs;
+  P.work = s + sc.work;
+  P.work_cap = sc.work_cap;
+  // Records of every slot (the state at the start and after the last step)
+  // and its sinks, checked per slot below: a slot with a non-finite result
+  // fails alone, and every slot's output is written either way.
+  const int64_t rec_every = n_steps > 0 ? n_steps : 1;
+  std::vector<std::vector<double>> rec(n);
+  std::vector<double> sk(3 * static_cast<size_t>(n), 0.0);
+  std::vector<double *> ro(n, nullptr), so(n, nullptr);
+  for (int k = 0; k < n; ++k) {
+    rec[k].assign(4 * static_cast<size_t>(hs[k]->N) * hs[k]->N, 0.0);
+    ro[k] = rec[k].data();
+    so[k] = sk.data() + 3 * k;
+  }
+  RunOptions opt;
+  opt.check_numeric = false;
+  opt.no_alloc = no_alloc;
+  rc = run_impl(hs, n, precision, flags, start, rho0s, dt_fs, n_steps, rec_every, P, hip_stream,
+                ro.data(), so.data(), opt);
+  if (rc) return rc;
+  std::string bad;
+  for (int k = 0; k < n; ++k) {
+    const size_t len = 2 * static_cast<size_t>(hs[k]->N) * hs[k]->N;
+    const double *fin = rec[k].data() + (n_steps > 0 ? len : 0);
+    bool ok = std::isfinite(so[k][0]) && std::isfinite(so[k][1]) && std::isfinite(so[k][2]);
+    for (size_t q = 0; ok && q < len; ++q) ok = std::isfinite(fin[q]);
+    if (!ok) bad += (bad.empty() ? "" : ", ") + std::to_string(k);
+    if (rho_out && rho_out[k]) std::memcpy(rho_out[k], fin, sizeof(double) * len);
+    if (sinks_out && sinks_out[k]) std::memcpy(sinks_out[k], so[k], sizeof(double) * 3);
+  }
+  if (!bad.empty())
+    return fail(HEOM_E_NUMERIC, "non-finite result in slot(s) " + bad +
+                                    " (every slot was advanced; the others are valid)");
+  return HEOM_OK;
 }
 
 }  // namespace
@@ -956,58 +1063,9 @@ int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int 
                        int64_t n_steps, void *d_scratch, size_t scratch_bytes, void *hip_stream,
                        double *const *rho_out, double *const *sinks_out) {
   try {
-    int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, 1,
-                          HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
-                              HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
-                              kShapeFlagMask);
-    if (rc) return rc;
-    if (!d_workspaces || !workspace_bytes || !start)
-      return fail(HEOM_E_INVALID, "workspaces, sizes and start flags are required");
-    const SlotScratch sc = slot_scratch(hs, n);
-    if (!d_scratch || reinterpret_cast<uintptr_t>(d_scratch) % kAlign || scratch_bytes < sc.total)
-      return fail(HEOM_E_WORKSPACE, "scratch missing, misaligned or too small: need " +
-                                        std::to_string(sc.total) + " bytes");
-    RunPlace P;
-    for (int k = 0; k < n; ++k) {
-      heom_hierarchy *h = hs[k];
-      const Layout L1 = make_layout(&h, 1, precision);
-      char *ws = static_cast<char *>(d_workspaces[k]);
-      if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign || workspace_bytes[k] < L1.total)
-        return fail(HEOM_E_WORKSPACE, "workspace " + std::to_string(k) +
-                                          " missing, misaligned or too small");
-      for (int j = 0; j < k; ++j)
-        if (d_workspaces[j] == d_workspaces[k])
-          return fail(HEOM_E_INVALID, "two slots share one workspace");
-      P.base.push_back(ws);
-      P.inst.push_back(L1.inst[0]);
-      P.header.push_back(ws + L1.header);
-      P.want.push_back(header_for(&h, 1, precision));
-      P.header_of.push_back(k);
-    }
-    char *s = static_cast<char *>(d_scratch);
-    P.descs = s + sc.descs;
-    P.work = s + sc.work;
-    P.work_cap = sc.work_cap;
-    // Records: the state at the start and after the last step.
-    const int64_t rec_every = n_steps > 0 ? n_steps : 1;
-    std::vector<std::vector<double>> rec(n);
-    std::vector<double *> ro(n, nullptr), so(n, nullptr);
-    for (int k = 0; k < n; ++k) {
-      if (rho_out && rho_out[k]) {
-        rec[k].assign(4 * static_cast<size_t>(hs[k]->N) * hs[k]->N, 0.0);
-        ro[k] = rec[k].data();
-      }
-      if (sinks_out) so[k] = sinks_out[k];
-    }
-    rc = run_impl(hs, n, precision, flags, start, rho0s, dt_fs, n_steps, rec_every, P, hip_stream,
-                  ro.data(), so.data());
-    if (rc) return rc;
-    for (int k = 0; k < n; ++k)
-      if (ro[k]) {
-        const size_t len = 2 * static_cast<size_t>(hs[k]->N) * hs[k]->N;
-        std::memcpy(rho_out[k], rec[k].data() + (n_steps > 0 ? len : 0), sizeof(double) * len);
-      }
-    return HEOM_OK;
+    return advance_slots_impl(hs, n, precision, flags, d_workspaces, workspace_bytes, start,
+                              rho0s, dt_fs, n_steps, d_scratch, scratch_bytes, hip_stream, rho_out,
+                              sinks_out, false);
   } catch (...) {
     return fail(HEOM_E_NOMEM, "host allocation failed");
   }

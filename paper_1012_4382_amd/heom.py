@@ -62,6 +62,16 @@ class HeomError(RuntimeError):
         self.status = status
 
 
+class SlotsNumericError(HeomError):
+    """heom_advance_slots advanced every slot, and some results are non-finite:
+    ``failed`` lists those slots; ``rhos`` and ``sinks`` hold every slot's
+    outputs (the other slots are valid and may be continued)."""
+
+    def __init__(self, where: str, message: str, rhos, sinks, failed):
+        super().__init__(HEOM_E_NUMERIC, where, message)
+        self.rhos, self.sinks, self.failed = rhos, sinks, failed
+
+
 class _System(ctypes.Structure):
     _fields_ = [
         ("n_sites", ctypes.c_int32),
@@ -350,36 +360,52 @@ def slots_scratch_bytes(hs) -> int:
     return out.value
 
 
+def _slots_call(hs, workspaces, start, rho0s, want_rho):
+    """Marshalled arguments of heom_advance_slots and its output arrays."""
+    n = len(hs)
+    DP = ctypes.POINTER(ctypes.c_double)
+    a = {"arr": (ctypes.c_void_p * n)(*[h.handle.value for h in hs]),
+         "wsp": (ctypes.c_void_p * n)(*[w.data_ptr() for w in workspaces]),
+         "wsb": (ctypes.c_size_t * n)(*[w.numel() * w.element_size() for w in workspaces]),
+         "st": (ctypes.c_int32 * n)(*[1 if s else 0 for s in start]),
+         "r0": (DP * n)(), "ro": (DP * n)(), "so": (DP * n)(), "keep": []}
+    for k in range(n):
+        if rho0s is not None and rho0s[k] is not None:
+            r = np.ascontiguousarray(np.asarray(rho0s[k], np.complex128)).view(np.float64)
+            a["keep"].append(r)
+            a["r0"][k] = _dp(r)
+    rhos = [np.zeros((h.N, h.N), np.complex128) for h in hs] if want_rho else None
+    sinks = np.zeros((n, 3))
+    for k in range(n):
+        if rhos is not None:
+            a["ro"][k] = _dp(rhos[k].view(np.float64))
+        a["so"][k] = sinks[k].ctypes.data_as(DP)
+    return a, rhos, sinks
+
+
+def _slots_status(status, where, rhos, sinks):
+    if status == HEOM_E_NUMERIC:
+        failed = [k for k in range(len(sinks)) if not np.all(np.isfinite(sinks[k])) or
+                  (rhos is not None and not np.all(np.isfinite(rhos[k])))]
+        raise SlotsNumericError(where, library().heom_last_error().decode(), rhos, sinks, failed)
+    _check(status, where)
+
+
 def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scratch,
                   precision="fp64", stream=None, kernel: str = "auto", graphs: bool = True,
                   want_rho: bool = True, tile_shape=None, autotune: bool = True,
                   stores=None):
-    """Runs heom_advance_slots.  Returns (list of final rho [N, N] | None, sinks [n, 3])."""
-    n = len(hs)
-    DP = ctypes.POINTER(ctypes.c_double)
-    wsp = (ctypes.c_void_p * n)(*[w.data_ptr() for w in workspaces])
-    wsb = (ctypes.c_size_t * n)(*[w.numel() * w.element_size() for w in workspaces])
-    st = (ctypes.c_int32 * n)(*[1 if s else 0 for s in start])
-    keep = []
-    r0 = (DP * n)()
-    for k in range(n):
-        if rho0s is not None and rho0s[k] is not None:
-            a = np.ascontiguousarray(np.asarray(rho0s[k], np.complex128)).view(np.float64)
-            keep.append(a)
-            r0[k] = _dp(a)
-    rhos = [np.zeros((h.N, h.N), np.complex128) for h in hs] if want_rho else None
-    sinks = np.zeros((n, 3))
-    ro, so = (DP * n)(), (DP * n)()
-    for k in range(n):
-        if rhos is not None:
-            ro[k] = _dp(rhos[k].view(np.float64))
-        so[k] = sinks[k].ctypes.data_as(DP)
-    arr = (ctypes.c_void_p * n)(*[h.handle.value for h in hs])
+    """Runs heom_advance_slots.  Returns (list of final rho [N, N] | None, sinks [n, 3]).
+    Raises SlotsNumericError when some slots' results are non-finite (every
+    slot was advanced), HeomError on any other failure."""
+    a, rhos, sinks = _slots_call(hs, workspaces, start, rho0s, want_rho)
     sptr, sbytes = _ws_args(scratch)
     flags = _flags(False, kernel, graphs, tile_shape, autotune, stores)
-    _check(library().heom_advance_slots(arr, n, PRECISIONS[precision], flags, wsp, wsb, st, r0,
-                                        float(dt_fs), int(n_steps), sptr, sbytes,
-                                        _stream_handle(stream), ro, so), "heom_advance_slots")
+    status = library().heom_advance_slots(a["arr"], len(hs), PRECISIONS[precision], flags,
+                                          a["wsp"], a["wsb"], a["st"], a["r0"], float(dt_fs),
+                                          int(n_steps), sptr, sbytes, _stream_handle(stream),
+                                          a["ro"], a["so"])
+    _slots_status(status, "heom_advance_slots", rhos, sinks)
     return rhos, sinks
 
 

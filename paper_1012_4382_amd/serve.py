@@ -11,7 +11,9 @@ final reduced density matrix and sink populations are copied to the host.
 
 The device work is behind a small backend interface (``admit``, ``advance``,
 ``release``); ``GpuBackend`` implements it with the HIP library.  Tests drive
-the engine with a backend of their own and a virtual clock.
+the engine with a backend of their own and a virtual clock.  ``advance``
+reports a failure per request; a request that failed leaves the engine, and
+no request is ever advanced twice in one iteration.
 """
 from __future__ import annotations
 
@@ -82,27 +84,42 @@ class GpuBackend:
         return {"h": h, "ws": ws, "started": False}
 
     def advance(self, reqs, slots, n_steps: int):
-        """Advances all slots by n_steps; returns (rho list, sinks array) in order."""
-        out_rho, out_sinks = [None] * len(reqs), np.zeros((len(reqs), 3))
+        """Advances all slots by n_steps.  Returns (rho list, sinks array,
+        error list) in order: error[i] is None, or the reason slot i failed
+        (its state is then not to be continued)."""
+        n = len(reqs)
+        out_rho, out_sinks, errors = [None] * n, np.zeros((n, 3)), [None] * n
         # One launch sequence per precision and time step.
         by_prec = {}
         for i, r in enumerate(reqs):
             by_prec.setdefault((r.precision, r.dt), []).append(i)
         for (prec, _dt), idx in by_prec.items():
             hs = [slots[i]["h"] for i in idx]
-            need = self._heom.slots_scratch_bytes(hs)
-            if self._scratch is None or self._scratch.numel() < need:
-                self._scratch = self._heom.allocate_workspace(max(need, 1 << 20),
-                                                              device=self.device)
-            rhos, sinks = self._heom.advance_slots(
-                hs, [slots[i]["ws"] for i in idx], [not slots[i]["started"] for i in idx],
-                [reqs[i].rho0 for i in idx], reqs[idx[0]].dt, n_steps, self._scratch,
-                precision=prec, stream=self.stream, kernel=self.kernel)
+            try:
+                need = self._heom.slots_scratch_bytes(hs)
+                if self._scratch is None or self._scratch.numel() < need:
+                    self._scratch = self._heom.allocate_workspace(max(need, 1 << 20),
+                                                                  device=self.device)
+                rhos, sinks = self._heom.advance_slots(
+                    hs, [slots[i]["ws"] for i in idx], [not slots[i]["started"] for i in idx],
+                    [reqs[i].rho0 for i in idx], reqs[idx[0]].dt, n_steps, self._scratch,
+                    precision=prec, stream=self.stream, kernel=self.kernel)
+                failed = set()
+            except self._heom.SlotsNumericError as e:
+                # Every slot of the call advanced; only the non-finite ones failed.
+                rhos, sinks, failed = e.rhos, e.sinks, set(e.failed)
+                for j in failed:
+                    errors[idx[j]] = f"non-finite result after {n_steps} more steps"
+            except Exception as e:  # the state of every slot of this call is unknown
+                for i in idx:
+                    errors[i] = str(e)
+                continue
             for j, i in enumerate(idx):
                 slots[i]["started"] = True
-                out_rho[i] = rhos[j]
-                out_sinks[i] = sinks[j]
-        return out_rho, out_sinks
+                if j not in failed:
+                    out_rho[i] = rhos[j]
+                    out_sinks[i] = sinks[j]
+        return out_rho, out_sinks, errors
 
     def release(self, slot) -> None:
         slot["ws"] = None
@@ -219,26 +236,28 @@ class Engine:
         k = min(self.chunk_steps, min(r.steps - r.steps_done for r, _, _ in self.active))
         reqs = [r for r, _, _ in self.active]
         slots = [s for _, s, _ in self.active]
-        try:
-            rhos, sinks = self.backend.advance(reqs, slots, k) if k > 0 else ([None] * len(reqs),
-                                                                              np.zeros((len(reqs), 3)))
-        except Exception:
-            # Isolate the failure: advance each request alone; only the ones
-            # that fail are dropped.
-            rhos, sinks = [None] * len(reqs), np.zeros((len(reqs), 3))
-            keep = []
-            for i, (r, s, nb) in enumerate(self.active):
-                try:
-                    rr, ss = self.backend.advance([r], [s], k)
-                    rhos[i], sinks[i] = rr[0], ss[0]
-                    keep.append(i)
-                except Exception as e:
-                    r.status, r.error, r.finish_s = "failed", str(e), self._now()
-                    self.finished.append(r)
-                    self._free(s, nb)
-            self.active = [self.active[i] for i in keep]
-            rhos = [rhos[i] for i in keep]
-            sinks = sinks[keep]
+        n = len(reqs)
+        if k > 0:
+            try:
+                rhos, sinks, errors = self.backend.advance(reqs, slots, k)
+            except Exception as e:
+                # The backend cannot say which requests advanced: none of them
+                # can be continued (re-running them could advance some twice).
+                rhos, sinks, errors = [None] * n, np.zeros((n, 3)), [str(e)] * n
+        else:
+            rhos, sinks, errors = [None] * n, np.zeros((n, 3)), [None] * n
+        # Failed requests leave the engine; every other one advanced by k.
+        keep = []
+        for i, (r, s, nb) in enumerate(self.active):
+            if errors[i] is None:
+                keep.append(i)
+                continue
+            r.status, r.error, r.finish_s = "failed", str(errors[i]), self._now()
+            self.finished.append(r)
+            self._free(s, nb)
+        self.active = [self.active[i] for i in keep]
+        rhos = [rhos[i] for i in keep]
+        sinks = sinks[keep]
         self.iterations += 1
         self.occupancy_sum += len(self.active)
         still = []

@@ -27,11 +27,15 @@ class VClock:
 class OracleBackend:
     """Engine backend on the oracle; 1 ns of virtual time per ADO-step."""
 
-    def __init__(self, clock, fail_ids=(), bytes_per_ado=1000):
+    def __init__(self, clock, fail_ids=(), bytes_per_ado=1000, raise_after=False):
         self.clock = clock
         self.fail_ids = set(fail_ids)
         self.bytes_per_ado = bytes_per_ado
+        # raise_after: a call that holds a failing request advances every
+        # state, then raises (the caller cannot tell which states moved).
+        self.raise_after = raise_after
         self.calls = []  # ids advanced together, per call
+        self.steps = {}  # id -> RK4 steps actually applied to its state
 
     def footprint(self, req):
         n, _ = oracle.count(req.system, req.depth)
@@ -42,18 +46,23 @@ class OracleBackend:
         return {"state": None, "n": n}
 
     def advance(self, reqs, slots, k):
+        """Every state advances by k steps; a request in fail_ids reports a
+        failure of its own (or, with raise_after, the whole call raises after
+        the states have moved)."""
         self.calls.append([r.id for r in reqs])
-        if any(r.id in self.fail_ids for r in reqs):
-            raise RuntimeError("device fault in a request")
-        rhos, sinks = [], np.zeros((len(reqs), 3))
+        rhos, sinks, errors = [], np.zeros((len(reqs), 3)), []
         for i, (r, s) in enumerate(zip(reqs, slots)):
             out = oracle.propagate(r.system, r.depth, r.rho0, r.dt, k, record_every=max(k, 1),
                                    want_state=True, state_in=s["state"], n_threads=1)
             s["state"] = out["state"]
+            self.steps[r.id] = self.steps.get(r.id, 0) + k
             rhos.append(out["rho"][-1])
             sinks[i] = out["scalars"]
+            errors.append("device fault in a request" if r.id in self.fail_ids else None)
         self.clock.t += k * sum(s["n"] for s in slots) * 1e-9
-        return rhos, sinks
+        if self.raise_after and any(e is not None for e in errors):
+            raise RuntimeError("launch failed after the states were advanced")
+        return rhos, sinks, errors
 
     def release(self, slot):
         slot["state"] = None
@@ -170,3 +179,43 @@ def test_one_at_a_time_baseline_and_finish_callback():
     assert all(len(c) == 1 for c in be.calls)
     assert [r.admit_s for r in reqs] == sorted(r.admit_s for r in reqs)
     assert reqs[1].admit_s >= reqs[0].finish_s
+
+
+def test_failed_slot_does_not_rerun_the_others():
+    """A request that fails inside a batched advance leaves alone; the requests
+    advanced with it are not advanced again, so their results are those of
+    the request run alone and their step counts match the steps applied."""
+    clock = VClock()
+    be = OracleBackend(clock, fail_ids={1})
+    eng = Engine(be, hbm_budget_bytes=10**9, chunk_steps=30, clock=clock, sleep=clock.sleep)
+    reqs = [_req(i, arrival=0.0, steps=90) for i in range(3)]
+    m = eng.run(reqs)
+    assert reqs[1].status == "failed" and "device fault" in reqs[1].error
+    assert m["completed"] == 2 and m["failed"] == 1
+    for r in (reqs[0], reqs[2]):
+        assert be.steps[r.id] == r.steps_done == r.steps
+        ref = oracle.propagate(r.system, r.depth, r.rho0, r.dt, r.steps, record_every=r.steps,
+                               n_threads=1)
+        assert np.array_equal(r.rho_final, ref["rho"][-1]), r.id
+        assert np.array_equal(r.sinks, ref["scalars"]), r.id
+    assert eng.in_use == 0
+
+
+def test_backend_exception_fails_the_call_without_rerun():
+    """When the backend raises after moving the states, the engine cannot tell
+    which requests advanced: every request of that call fails, none is run
+    again, and no result is reported for them."""
+    clock = VClock()
+    be = OracleBackend(clock, fail_ids={1}, raise_after=True)
+    eng = Engine(be, hbm_budget_bytes=10**9, chunk_steps=30, clock=clock, sleep=clock.sleep)
+    reqs = [_req(i, arrival=0.0, steps=90) for i in range(3)]
+    late = _req(5, arrival=1.0, steps=60)  # arrives after the failure, runs normally
+    m = eng.run(reqs + [late])
+    assert all(r.status == "failed" for r in reqs)
+    assert len(be.calls) == 3 and be.calls[0] == [0, 1, 2]  # one call, then `late` alone
+    assert all(be.steps[r.id] == 30 for r in reqs)  # advanced once, never re-run
+    assert late.status == "done" and m["completed"] == 1 and m["failed"] == 3
+    ref = oracle.propagate(late.system, late.depth, late.rho0, 1.0, 60, record_every=60,
+                           n_threads=1)
+    assert np.array_equal(late.sinks, ref["scalars"])
+    assert eng.in_use == 0
