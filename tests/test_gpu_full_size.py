@@ -2,10 +2,13 @@
 
 The benchmark's HBM-resident shape (7 sites, depth 16: 245157 ADOs, the
 paper's largest hierarchy) and the serving workload's largest request (24
-sites, depth 4: 20475 ADOs) are propagated for two RK4 steps by the launch
-configuration the benchmark uses (the autotuned LDS-tiled kernels), and every
-ADO, matched by multi-index, is compared with the FP64 oracle.  After two
-steps every ADO up to tier 8 is nonzero, and at depth 4 all of them are.
+sites, depth 4: 20475 ADOs) are propagated by the launch configuration the
+benchmark uses (the autotuned LDS-tiled kernels), and every ADO, matched by
+multi-index, is compared with the FP64 oracle tier by tier: tier |n| = t
+relative to its own largest entry, so the deep tiers (whose entries are many
+orders of magnitude below sigma_0's) are really compared.  Each RK4 step is a
+degree-4 polynomial of the generator, so after s steps tiers up to 4s are
+nonzero: 4 steps reach tier 16 at depth 16, and 2 steps tier 4 (all of depth 4).
 """
 import sys
 
@@ -14,6 +17,7 @@ import pytest
 
 import oracle
 from paper_1012_4382_amd import heom, workloads
+from tiers import assert_tiers, match_oracle_order, tier_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -42,31 +46,25 @@ def _compare_full_state(sys_, depth, rho0, steps, dt=1.0):
     ref = oracle.propagate(sys_, depth, rho0, dt, steps, record_every=steps, want_state=True)
     osig, osc = ref["state"]
     multi, _, _ = h.tables()
-    omulti = oracle.enumerate_ados(sys_, depth)
-    index = {tuple(int(v) for v in r): i for i, r in enumerate(omulti)}
-    perm = np.array([index[tuple(int(v) for v in r)] for r in multi])
-    assert len(set(perm.tolist())) == h.n_ados == len(omulti)
+    perm = match_oracle_order(multi, oracle.enumerate_ados(sys_, depth))
     want = osig[perm]
-    scale = float(np.max(np.abs(want)))
-    err = float(np.max(np.abs(sig - want)))
-    assert err <= FP64_TOL * scale, (err, scale)
-    assert np.max(np.abs(sc - osc)) <= FP64_TOL
-    # Nonzero deep tiers: the comparison is not between zeros.
-    tiers = np.sum(multi, axis=1)
-    deepest = int(np.max(tiers[np.max(np.abs(sig), axis=(1, 2)) > 0]))
+    for t, err, scale in tier_errors(multi, sig, want):
+        _say(f"  tier {t}: max |ref| {scale:.3e}, max err {err:.3e}")
+    deepest = assert_tiers(multi, sig, want, FP64_TOL)
+    assert np.max(np.abs(sc - osc)) <= FP64_TOL * np.max(np.abs(osc))
     return h.n_ados, deepest
 
 
-def test_depth16_full_state_two_steps():
+def test_depth16_full_state_four_steps():
     w = workloads.fmo_like(seed=0, site=1, depth=16)
-    _say("case: N=7 depth 16 (245157 ADOs), 2 steps, full state vs oracle")
-    n, deepest = _compare_full_state(w["system"], 16, w["rho0"], 2)
-    assert n == 245157 and deepest == 8
+    _say("case: N=7 depth 16 (245157 ADOs), 4 steps, full state vs oracle per tier")
+    n, deepest = _compare_full_state(w["system"], 16, w["rho0"], 4)
+    assert n == 245157 and deepest == 16
 
 
 def test_24site_depth4_full_state_two_steps():
     w = next(r for r in workloads.serving_trace(200)
              if r["system"]["H"].shape[0] == 24 and r["depth"] == 4)
-    _say("case: 24-site ring depth 4 (20475 ADOs), 2 steps, full state vs oracle")
+    _say("case: 24-site ring depth 4 (20475 ADOs), 2 steps, full state vs oracle per tier")
     n, deepest = _compare_full_state(w["system"], 4, w["rho0"], 2)
     assert n == 20475 and deepest == 4
