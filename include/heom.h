@@ -209,6 +209,32 @@ int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int 
                        int64_t n_steps, void *d_scratch, size_t scratch_bytes, void *hip_stream,
                        double *const *rho_out, double *const *sinks_out);
 
+/* heom_advance_slots for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and results without d_scratch.  The
+ * launch's descriptors and work list go to a static device array of the
+ * library (2 MiB per GPU, held until the process ends); slots that need more
+ * (heom_slots_scratch_bytes > 2 MiB, about 2.9 million ADOs in all) are
+ * rejected with HEOM_E_WORKSPACE.  The call allocates no device memory and
+ * creates no stream, event or graph:
+ *   - every hierarchy must already have its neighbour tables on this device,
+ *     i.e. have been used here by an allocating call (heom_propagate,
+ *     heom_propagate_batch or heom_advance_slots); otherwise
+ *     HEOM_E_UNSUPPORTED and nothing runs;
+ *   - launch shapes come from the autotuner's entries of this process (or
+ *     its cache file), else the defaults; no timing runs are made (results
+ *     do not depend on the shape);
+ *   - every stage kernel is launched directly on hip_stream.
+ * All calls on one GPU share that GPU's static array, whose contents the
+ * next call overwrites in full: calls that overlap on one GPU (from several
+ * host threads or on several streams) race and must be serialised by the
+ * caller. */
+int heom_advance_slots_noalloc(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
+                               void *const *d_workspaces, const size_t *workspace_bytes,
+                               const int32_t *start, const double *const *rho0s, double dt_fs,
+                               int64_t n_steps, void *hip_stream, double *const *rho_out,
+                               double *const *sinks_out);
+
 /* Energy-transfer efficiency (eq:eta) and mean trapping time (eq:trappingtime)
  * for an excitation starting in rho0.
  *   t_end_fs > 0   propagate to this fixed time (rounded to whole steps)

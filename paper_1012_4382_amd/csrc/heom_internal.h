@@ -98,6 +98,10 @@ enum class KernelKind { kTile, kLane, kGeneric };
 constexpr int kWideShape = 5;
 constexpr int kMaxTileShapes = kWideShape + 1;
 
+// Size of the static device scratch of the allocation-free entry point
+// (descriptors and work list of one call).
+constexpr size_t kStaticScratchBytes = size_t{2} << 20;
+
 // A block of ADOs of one instance: blockIdx.x -> (instance, first ADO).
 // first = -1 marks the sigma_0 item of an FP32-mixed tile launch.
 struct WorkItem {

@@ -1,6 +1,9 @@
 // kernels_dispatch.hip -- launch entry points of the stage, initialisation and
 // snapshot kernels used by the host runtime (runtime.cpp).  The tile and lane
 // kernel instances live in the kernels_tile_*.hip and kernels_lane.hip units.
+#include <map>
+#include <mutex>
+
 #include "stage_kernels.h"
 
 namespace heom {
@@ -177,6 +180,33 @@ hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(n_items), dim3(block), 0, stream, descs, work, stage, coef, hist_slot);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free entry point (heom_advance_slots_noalloc):
+// the descriptors and work list of its launches, rewritten in full by every
+// call (nothing in it needs to start at zero).  Each GPU the library runs on
+// holds its own copy until the process ends.  Host code never uses the name
+// `scratch` as an address: it takes the device address that
+// hipGetSymbolAddress returns for the current device, once per device.
+namespace {
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+}  // namespace
+
+hipError_t static_scratch(int device, void **ptr) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *ptr = it->second;
+    return hipSuccess;
+  }
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  *ptr = p;
+  return hipSuccess;
 }
 
 hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,

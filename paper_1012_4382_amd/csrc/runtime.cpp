@@ -33,6 +33,7 @@ hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, 
                        int block, hipStream_t stream);
 hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
                            hipStream_t stream);
+hipError_t static_scratch(int device, void **ptr);
 
 namespace {
 
@@ -1066,6 +1067,24 @@ int heom_advance_slots(heom_hierarchy *const *hs, int32_t n, int precision, int 
     return advance_slots_impl(hs, n, precision, flags, d_workspaces, workspace_bytes, start,
                               rho0s, dt_fs, n_steps, d_scratch, scratch_bytes, hip_stream, rho_out,
                               sinks_out, false);
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+}
+
+int heom_advance_slots_noalloc(heom_hierarchy *const *hs, int32_t n, int precision, int flags,
+                               void *const *d_workspaces, const size_t *workspace_bytes,
+                               const int32_t *start, const double *const *rho0s, double dt_fs,
+                               int64_t n_steps, void *hip_stream, double *const *rho_out,
+                               double *const *sinks_out) {
+  try {
+    int device = 0;
+    HEOM_HIP(hipGetDevice(&device), "hipGetDevice");
+    void *scratch = nullptr;
+    HEOM_HIP(static_scratch(device, &scratch), "hipGetSymbolAddress(scratch)");
+    return advance_slots_impl(hs, n, precision, flags, d_workspaces, workspace_bytes, start,
+                              rho0s, dt_fs, n_steps, scratch, kStaticScratchBytes, hip_stream,
+                              rho_out, sinks_out, true);
   } catch (...) {
     return fail(HEOM_E_NOMEM, "host allocation failed");
   }

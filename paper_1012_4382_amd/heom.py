@@ -117,6 +117,9 @@ _SIGNATURES = [
     ("heom_advance_slots", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, ctypes.c_int, _P(_vp),
                                           _P(_sz), _P(_i32), _P(_P(_d)), _d, _i64, _vp, _sz, _vp,
                                           _P(_P(_d)), _P(_P(_d))]),
+    ("heom_advance_slots_noalloc", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, ctypes.c_int,
+                                                  _P(_vp), _P(_sz), _P(_i32), _P(_P(_d)), _d,
+                                                  _i64, _vp, _P(_P(_d)), _P(_P(_d))]),
     ("heom_tile_shape_count", ctypes.c_int, []),
     ("heom_tile_shape_info", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i32, _P(_i32), _P(_i32),
                                             _P(_i32), _P(_i32), _P(_i32)]),
@@ -361,7 +364,7 @@ def slots_scratch_bytes(hs) -> int:
 
 
 def _slots_call(hs, workspaces, start, rho0s, want_rho):
-    """Marshalled arguments of heom_advance_slots and its output arrays."""
+    """Marshalled arguments of heom_advance_slots(_noalloc) and its output arrays."""
     n = len(hs)
     DP = ctypes.POINTER(ctypes.c_double)
     a = {"arr": (ctypes.c_void_p * n)(*[h.handle.value for h in hs]),
@@ -406,6 +409,22 @@ def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scra
                                           int(n_steps), sptr, sbytes, _stream_handle(stream),
                                           a["ro"], a["so"])
     _slots_status(status, "heom_advance_slots", rhos, sinks)
+    return rhos, sinks
+
+
+def advance_slots_noalloc(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int,
+                          precision="fp64", stream=None, kernel: str = "auto",
+                          want_rho: bool = True, tile_shape=None, autotune: bool = True,
+                          stores=None):
+    """Runs heom_advance_slots_noalloc (no scratch argument; nothing is
+    allocated on the device).  Returns and raises as advance_slots."""
+    a, rhos, sinks = _slots_call(hs, workspaces, start, rho0s, want_rho)
+    flags = _flags(False, kernel, True, tile_shape, autotune, stores)
+    status = library().heom_advance_slots_noalloc(a["arr"], len(hs), PRECISIONS[precision],
+                                                  flags, a["wsp"], a["wsb"], a["st"], a["r0"],
+                                                  float(dt_fs), int(n_steps),
+                                                  _stream_handle(stream), a["ro"], a["so"])
+    _slots_status(status, "heom_advance_slots_noalloc", rhos, sinks)
     return rhos, sinks
 
 
