@@ -18,9 +18,10 @@ runs against the oracle's stored trajectories, and the oracle timed on this
 host (1 thread and all threads) on a bounded sample.  Further legs, each
 skippable: the FMO-shaped 8-solve batch at depth 7 (5 ps, eta) with its own
 roofline, single-solve and FP32-mixed rates, the depth-16 and 24-site sizing
-launches, batch scaling (2-128 solves and a plain device copy for scale), the
-precision comparison against the oracle, and the 200-request serving trace in
-FP64 and FP32-mixed.
+launches, the depth-16 hierarchy split over 8 ranks, the scaled hierarchy and
+its filter at depths 12 and 16, batch scaling (2-128 solves and a plain device
+copy for scale), the precision comparison against
+the oracle, and the 200-request serving trace in FP64 and FP32-mixed.
 """
 from __future__ import annotations
 
@@ -422,6 +423,80 @@ def _wide_sizing(heom, torch, workloads, stream, kernel):
     return out
 
 
+def _shard_sizing(heom, torch, workloads, stream, ranks=8, steps=100):
+    """The paper's largest shape (7 sites, depth 16, 245157 ADOs) split over
+    `ranks` contiguous ranges of its ADO order, as a multi-GPU run would place
+    it, and run on this one GPU: per rank its share, its halo (ADOs of other
+    ranks it links to) and the bytes an exchange of it moves per RK4 stage,
+    against the bytes its own share moves; and the stage time of the split
+    launch (halo copies included) against the unsplit one."""
+    w = workloads.fmo_like(seed=0, site=1, depth=16, steps=steps)
+    h = heom.Hierarchy(w["system"], w["depth"])
+    N = h.N
+    sh = heom.Shard(h, ranks)
+    rows = []
+    for r in range(ranks):
+        inf = sh.info(r)
+        local_moved = inf["n_local"] * MOVED_ADOS_PER_LAUNCH * N * N * 8
+        rows.append({**inf, "halo_bytes_per_stage": inf["halo_reals"] * 8,
+                     "halo_bytes_min_per_stage": inf["halo_reals_min"] * 8,
+                     "halo_min_over_local_moved": inf["halo_reals_min"] * 8 / local_moved})
+    ws = heom.allocate_workspace(sh.workspace_bytes)
+    heom.propagate_sharded(sh, w["rho0"], 1.0, 20, record_every=20, workspace=ws, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    heom.propagate_sharded(sh, w["rho0"], 1.0, steps, record_every=steps, workspace=ws,
+                           stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    split_us = ev0.elapsed_time(ev1) * 1e3 / (4 * steps)
+    unsplit_ms, _ = _stage_kernel_timing(heom, torch, [h], [w["rho0"]], stream, "auto", "fp64",
+                                         steps=steps)
+    sh.close()
+    return {"workload": "fmo_like_7site_depth16_split", "n_ados": h.n_ados, "ranks": ranks,
+            "rows": rows, "split_stage_us": split_us, "unsplit_stage_us": unsplit_ms * 1e3,
+            "halo_copy_bytes_per_stage": sum(r["halo_bytes_min_per_stage"] for r in rows) * 2}
+
+
+def _scaled_filtered(heom, torch, workloads, stream, depths=(12, 16), tols=(1e-6, 1e-8, 1e-10),
+                     steps=5000):
+    """The scaled hierarchy and its filter on the FMO-shaped 7-site solve
+    (seed 0, site 1, 300 K) at depths 12 and 16 over 5 ps: eta and the share
+    of ADOs the filter keeps (nonzero at the end of the run) per threshold,
+    against the unfiltered scaled run and the plain (unscaled) run."""
+    out = {"workload": "fmo_like_7site_seed0_site1_5ps", "rk4_steps": steps, "rows": []}
+    for D in depths:
+        w = workloads.fmo_like(seed=0, site=1, depth=D, steps=steps)
+        h0 = heom.Hierarchy(w["system"], D)
+        t0 = time.perf_counter()
+        _, s0, _ = heom.propagate(h0, w["rho0"], 1.0, steps, record_every=steps, stream=stream)
+        plain_s = time.perf_counter() - t0
+        h0.close()
+        row = {"depth": D, "n_ados": None, "eta_plain": float(s0[0]), "plain_seconds": plain_s,
+               "filtered": []}
+        for tol in (0.0,) + tuple(tols):
+            h = heom.Hierarchy(w["system"], D, scaled=True, filter_tol=tol)
+            row["n_ados"] = h.n_ados
+            t0 = time.perf_counter()
+            _, sk, ws = heom.propagate(h, w["rho0"], 1.0, steps, record_every=steps,
+                                       stream=stream)
+            el = time.perf_counter() - t0
+            sig, _ = heom.read_state(h, ws, stream=stream)
+            nz = np.max(np.abs(sig), axis=(1, 2)) > 0
+            kept = int(np.sum(nz))
+            tiers = np.sum(h.tables()[0], axis=1)
+            by_tier = [int(np.sum(nz[tiers == t])) for t in range(D + 1)]
+            del sig, ws
+            entry = {"filter_tol": tol, "eta": float(sk[0]),
+                     "abs_eta_error_vs_plain": abs(float(sk[0]) - float(s0[0])),
+                     "ados_nonzero_at_end": kept, "kept_fraction": kept / h.n_ados,
+                     "nonzero_by_tier": by_tier, "seconds": el}
+            row["filtered"].append(entry)
+            h.close()
+        out["rows"].append(row)
+    return out
+
+
 def _batch_scaling(heom, torch, workloads, stream, kernel, sizes=(2, 4, 8, 16, 32, 64, 128)):
     """The FMO-shaped workload with more solves per launch sequence (seeds
     0..n/2-1, sites 1 and 6): where the stage kernel leaves the latency-bound
@@ -607,6 +682,8 @@ def main():
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
         result["wide_sizing"] = _wide_sizing(heom, torch, workloads, stream, args.kernel)
+        result["shard_sizing"] = _shard_sizing(heom, torch, workloads, stream)
+        result["scaled_filtered"] = _scaled_filtered(heom, torch, workloads, stream)
     if not args.no_batch_scaling:
         result["batch_scaling"] = _batch_scaling(heom, torch, workloads, stream, args.kernel)
     if not args.no_variants:

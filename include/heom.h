@@ -118,6 +118,26 @@ typedef struct {
  * On success *out owns the handle; release it with heom_destroy. */
 int heom_build_hierarchy(const heom_system *sys, int32_t depth, heom_hierarchy **out);
 
+/* heom_build_hierarchy for the scaled hierarchy, the form the introduction
+ * names as the way to fewer auxiliary matrices (its reference [Zhu 2011]).
+ * Every ADO n is held divided by w_n = sqrt(prod_m n_m! |c_m|^n_m), which
+ * leaves sigma_0 unchanged and makes the ADOs of one size, so that a single
+ * threshold can drop the negligible ones: in eq:lab8 the coupling to n + e_m
+ * gains the factor sqrt((n_m + 1)|c_m|) and the coupling to n - e_m has
+ * sqrt(n_m / |c_m|) in the place of n_m.  The weights are tabulated per mode
+ * and occupation on the host.
+ *   filter_tol  0: no filter; > 0: after every RK4 step each ADO n != 0 whose
+ *               stored entries (real and imaginary parts) are all below
+ *               filter_tol in absolute value is set to zero
+ * The propagation entry points accept the handle like any other; its stages
+ * run on the LDS-tiled wide kernel (real H, N <= 32, K + 1 <= 4), otherwise
+ * HEOM_E_UNSUPPORTED.  rho (sigma_0) and the sinks are those of the unscaled
+ * equations; heom_read_state returns the scaled ADOs.  Errors as
+ * heom_build_hierarchy; HEOM_E_INVALID also for a negative or non-finite
+ * filter_tol or a zero bath amplitude (lambda = 0). */
+int heom_build_hierarchy_scaled(const heom_system *sys, int32_t depth, double filter_tol,
+                                heom_hierarchy **out);
+
 /* Sizes of a built hierarchy.  Any output pointer may be NULL.
  *   n_ados      number of ADOs, C(M + depth, depth)
  *   n_modes     M = N * (K + 1)
@@ -251,6 +271,51 @@ int heom_efficiency(heom_hierarchy *h, int precision, const double *rho0, double
  * followed by 3 doubles {P_trap, P_recomb, Q}.  Synchronises hip_stream. */
 int heom_read_state(const heom_hierarchy *h, int precision, const void *d_workspace,
                     size_t workspace_bytes, void *hip_stream, double *state_out);
+
+/* A hierarchy split over ranks: the one-GPU part of propagating a hierarchy
+ * too large for one GPU on several.  Every ADO is linked to its neighbours
+ * n +- e_m (eq:lab8; Appendix B: each matrix is connected to 2N neighbours),
+ * and all of them are accessed in every step (Appendix B), so a split
+ * hierarchy must exchange, before every RK4 stage, the stage input of the
+ * ADOs each rank links to but does not hold: its halo (the communication that
+ * the introduction names as what limits CPU clusters).
+ *
+ * heom_shard_build splits h into n_ranks contiguous ranges of its ADO order
+ * (equal sizes rounded to 64-ADO tiles; rank 0 holds sigma_0; at least 64 ADOs
+ * per rank).  Each rank becomes an instance of its own whose neighbour tables
+ * point at its own ADOs and at halo slots after them.  Host-only work; h is
+ * only read and may be destroyed afterwards.  Errors: HEOM_E_INVALID,
+ * HEOM_E_NOMEM.  Release the result with heom_shard_destroy (NULL-safe). */
+typedef struct heom_shard heom_shard; /* opaque, library-owned */
+typedef struct {
+  int64_t first_ado;      /* first ADO of the rank's range in h's order          */
+  int64_t n_local;        /* ADOs the rank holds                                 */
+  int64_t n_halo;         /* ADOs of other ranks it links to (halo ADOs)         */
+  int64_t cut_links;      /* links n -> n +- e_m from its ADOs to halo ADOs      */
+  int64_t halo_reals;     /* reals of its halo ADOs in full: n_halo * N * N      */
+  int64_t halo_reals_min; /* reals it needs and receives per RK4 stage: of each
+                             halo ADO only the rows and columns of the sites whose
+                             modes link to it (the entries the stage reads)      */
+} heom_shard_rank_info;
+int heom_shard_build(const heom_hierarchy *h, int32_t n_ranks, heom_shard **out);
+int heom_shard_info(const heom_shard *s, int32_t rank, heom_shard_rank_info *out);
+/* Workspace for heom_propagate_sharded (every rank's state and halo slots,
+ * the halo list).  FP64 only: HEOM_E_UNSUPPORTED for other precisions. */
+int heom_shard_workspace_bytes(const heom_shard *s, int precision, size_t *bytes);
+/* heom_propagate for a split hierarchy on the current device: before each RK4
+ * stage a copy kernel fills every rank's halo slots (halo_reals_min reals per
+ * rank) from the owning ranks' stage inputs, standing in for the exchange
+ * between GPUs; then one stage launch runs every rank's share.  Arguments, outputs and errors as
+ * heom_propagate (precision HEOM_FP64 only); the results equal those of
+ * heom_propagate on h bitwise. */
+int heom_propagate_sharded(heom_shard *s, int precision, int flags, const double *rho0,
+                           double dt_fs, int64_t n_steps, int64_t record_every, void *d_workspace,
+                           size_t workspace_bytes, void *hip_stream, double *rho_out,
+                           double *sinks_out);
+/* heom_read_state for a split hierarchy: the full state in h's order. */
+int heom_read_state_sharded(const heom_shard *s, int precision, const void *d_workspace,
+                            size_t workspace_bytes, void *hip_stream, double *state_out);
+void heom_shard_destroy(heom_shard *s);
 
 /* Launch shapes of the LDS-tiled stage kernels and their autotuner.
  *

@@ -36,7 +36,7 @@ TILE_F64_FLAGS = ["-mllvm", "-amdgpu-kernarg-preload-count=8"]
 # per storage precision.
 _SHAPES = 5
 SOURCES = ([("params.cpp", None, None), ("hierarchy.cpp", None, None),
-            ("runtime.cpp", None, None), ("autotune.cpp", None, None),
+            ("runtime.cpp", None, None), ("autotune.cpp", None, None), ("shard.cpp", None, None),
             ("kernels_dispatch.hip", None, None), ("kernels_lane.hip", None, None)] +
            [(f"kernels_tile_{u}.hip", s, f64) for u in ("small", "7", "8")
             for s in range(_SHAPES) for f64 in (True, False)] +

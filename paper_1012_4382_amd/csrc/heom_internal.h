@@ -49,6 +49,11 @@ HEOM_HD inline int pair_index(int N, int a, int b) {  // a < b
 //   [.., +N*N)         packed rho0 (used by the initialisation kernel)
 //   [.., +ceil(R/2))   FP32 copy of the first R = rho0 entries, two floats
 //                      per double (read by the FP32 stage kernels)
+// and, for a scaled hierarchy (ADOs held divided by
+// w_n = sqrt(prod_m n_m! |c_m|^n_m)), from `total` on, with L = depth + 1:
+//   [total, +M*L)      up-coupling weight of mode m at occupation v,
+//                      sqrt((v + 1)|c_m|), at m * L + v
+//   [.., +M*L)         down-coupling weight, sqrt(v / |c_m|) (n_m's place)
 struct ParamOffsets {
   int h_re, h_im, half_gamma, delta, trap, rec, c_re, c_im, nu, rho0, f32, total;
 };
@@ -72,6 +77,13 @@ HEOM_HD inline ParamOffsets param_offsets(int N, int M) {
 // Scalars carried with each state buffer: P_trap, P_rec, Q = int P_trap dt.
 constexpr int kScalars = 4;  // padded
 
+// InstDesc::flags: the instance's ADO 0 is not sigma_0 (one rank's share of
+// a hierarchy split over ranks: sigma_0, the sinks and the records live on the
+// rank that holds the first ADOs).
+constexpr int32_t kInstNoSigma0 = 1;
+// The instance holds the scaled ADOs (coupling weights after the parameters).
+constexpr int32_t kInstScaled = 2;
+
 // Device descriptor of one instance (lives in the workspace).
 struct InstDesc {
   void *y, *a, *b;            // planes of the state and the two stage buffers (T*)
@@ -82,7 +94,19 @@ struct InstDesc {
   const int32_t *up, *down;   // [M][stride]
   const uint8_t *occ;         // [M][stride]
   int64_t n_ados, stride;
-  int32_t N, M, KP, pad_;
+  int32_t N, M, KP, flags;
+  int32_t levels, pad_;  // scaled: occupations 0 .. levels - 1 in the weight tables
+  double filter_tol;     // > 0: ADOs below it are zeroed after every step
+};
+
+// One halo ADO of a split hierarchy: before each stage, ADO src_index of
+// instance src (its owner) is copied to slot dst_index of instance dst, in the
+// stage's input buffer; only the rows and columns of the sites in `sites`
+// (bit s for site s), the only entries the stage reads of it: element (a, b)
+// of a neighbour along a mode of site s is used only where s is a or b.
+struct HaloEntry {
+  int32_t dst, dst_index, src, src_index;
+  uint64_t sites;
 };
 
 // Stage kernel variants.
@@ -120,6 +144,8 @@ struct heom_hierarchy {
   int N = 0, K = 0, KP = 1, M = 0, depth = 0;
   int64_t n_ados = 0, stride = 0;
   bool h_real = true;
+  bool scaled = false;      // ADOs held divided by w_n; weights after the parameters
+  double filter_tol = 0.0;  // > 0: filter after every step (scaled hierarchies)
   double energy_offset = 0.0;  // removed mean site energy, rad/fs
   std::vector<double> params;  // ParamOffsets layout without rho0 filled
   std::vector<int32_t> site;   // [M]
@@ -137,6 +163,24 @@ struct heom_hierarchy {
   mutable std::vector<DeviceTables> dev;
 };
 
+// A hierarchy split over ranks: rank r owns the contiguous range
+// [first[r], first[r + 1]) of the ADO order and is an instance of its own,
+// whose tables point at its own ADOs (local index i - first[r]) and at halo
+// slots n_local, n_local + 1, ... that hold copies of the other ranks' ADOs it
+// couples to.  Rank 0 holds sigma_0.
+struct heom_shard {
+  int n_ranks = 0;
+  int N = 0, M = 0;
+  int64_t n_ados = 0;
+  std::vector<heom_hierarchy *> rank;  // owned; n_ados = local ADOs, stride covers the halo
+  std::vector<int64_t> first;          // [n_ranks + 1]
+  std::vector<heom::HaloEntry> halo;   // every rank's halo, rank by rank
+  struct Stats {
+    int64_t n_halo = 0, cut_links = 0, halo_reals_min = 0;
+  };
+  std::vector<Stats> stats;
+};
+
 namespace heom {
 
 // Thread-local error text.
@@ -147,6 +191,8 @@ int fail(int status, const std::string &msg);
 int build_params(const heom_system *sys, heom_hierarchy *h);
 // hierarchy.cpp
 int build_tables(heom_hierarchy *h);
+// shard.cpp
+int build_shard(const heom_hierarchy *h, int n_ranks, heom_shard *s);
 // kernels_dispatch.hip: whether launch shape `shape` exists for (N, K+1,
 // storage), and its ADOs per work item, threads per workgroup, elements per
 // wave, load chunk and minimum waves per SIMD (any output may be NULL).

@@ -90,25 +90,29 @@ bool has_fixed_kernel(int N, int KP) { return lane_kernel_ptr(N, KP, false) != n
 
 bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false, 0) != nullptr; }
 
-// The wide kernel's LDS (tile, Hamiltonian, tables) must fit the 160 KB of a
-// gfx950 CU.
-bool has_wide_kernel(int N, int M, bool mixed) {
+// The wide kernel's LDS (tile, Hamiltonian, tables, and for scaled
+// hierarchies `levels` weights per mode) must fit the 160 KB of a gfx950 CU.
+bool has_wide_kernel(int N, int M, bool mixed, int levels) {
   constexpr int kLdsBytes = 160 * 1024;
   return N >= 1 && N <= kWideMaxN && M % N == 0 && M / N <= kWideMaxKP &&
-         wide_lds(N, M, mixed ? 4 : 8).total <= kLdsBytes;
+         wide_lds(N, M, mixed ? 4 : 8, levels).total <= kLdsBytes;
 }
 
 namespace {
-template <typename T>
-const void *wide_kernel(int KP) {
+template <typename T, bool SCALED>
+const void *wide_kernel_of(int KP) {
   static_assert(kWideMaxKP == 4, "one instance per K+1");
   switch (KP) {
-    case 1: return reinterpret_cast<const void *>(&stage_wide<T, 1>);
-    case 2: return reinterpret_cast<const void *>(&stage_wide<T, 2>);
-    case 3: return reinterpret_cast<const void *>(&stage_wide<T, 3>);
-    case 4: return reinterpret_cast<const void *>(&stage_wide<T, 4>);
+    case 1: return reinterpret_cast<const void *>(&stage_wide<T, 1, SCALED>);
+    case 2: return reinterpret_cast<const void *>(&stage_wide<T, 2, SCALED>);
+    case 3: return reinterpret_cast<const void *>(&stage_wide<T, 3, SCALED>);
+    case 4: return reinterpret_cast<const void *>(&stage_wide<T, 4, SCALED>);
   }
   return nullptr;
+}
+const void *wide_kernel(bool mixed, int KP, bool scaled) {
+  if (mixed) return scaled ? wide_kernel_of<float, true>(KP) : wide_kernel_of<float, false>(KP);
+  return scaled ? wide_kernel_of<double, true>(KP) : wide_kernel_of<double, false>(KP);
 }
 }  // namespace
 
@@ -116,7 +120,7 @@ bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threa
                      int *elems_per_wave, int *chunk, int *min_waves) {
   int a, t, e, c, w;
   if (shape == kWideShape) {
-    if (!has_wide_kernel(N, N * KP, mixed)) return false;
+    if (!has_wide_kernel(N, N * KP, mixed, 0)) return false;
     const int P = N * (N + 1) / 2;
     a = kWideAdos;
     t = 64 * kWideWaves;
@@ -142,29 +146,31 @@ bool tile_shape_info(int N, int KP, bool mixed, int shape, int *ados, int *threa
 
 // Dynamic LDS beyond the default limit has to be allowed per kernel; done
 // once per configuration before any launch (and before graph capture).
-hipError_t prepare_wide(int N, int M, bool mixed) {
-  const int bytes = wide_lds(N, M, mixed ? 4 : 8).total;
-  const void *k = mixed ? wide_kernel<float>(M / N) : wide_kernel<double>(M / N);
+hipError_t prepare_wide(int N, int M, bool mixed, int levels) {
+  const int bytes = wide_lds(N, M, mixed ? 4 : 8, levels).total;
+  const void *k = wide_kernel(mixed, M / N, levels > 0);
   if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // `streaming` selects the tile kernel instance with non-temporal output
 // stores (built for FP64 storage; the wide, lane and generic kernels always
-// store plainly).
+// store plainly).  `levels` > 0: the group holds scaled hierarchies (wide
+// kernel only) with weight tables of that many occupations per mode.
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
-                        int stage, double coef, int hist_slot, bool streaming,
+                        int stage, double coef, int hist_slot, bool streaming, int levels,
                         hipStream_t stream) {
   if (kind == KernelKind::kTile && shape == kWideShape) {
-    const size_t lds = static_cast<size_t>(wide_lds(N, N * KP, mixed ? 4 : 8).total);
-    const StageKernel k = reinterpret_cast<StageKernel>(
-        const_cast<void *>(mixed ? wide_kernel<float>(KP) : wide_kernel<double>(KP)));
+    const size_t lds = static_cast<size_t>(wide_lds(N, N * KP, mixed ? 4 : 8, levels).total);
+    const StageKernel k =
+        reinterpret_cast<StageKernel>(const_cast<void *>(wide_kernel(mixed, KP, levels > 0)));
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(n_items), dim3(block), lds, stream, descs, work, stage, coef,
                        hist_slot);
     return hipGetLastError();
   }
+  if (levels > 0) return hipErrorInvalidValue;  // scaled: the wide kernel only
   StageKernel k = nullptr;
   switch (kind) {
     case KernelKind::kTile:
@@ -215,6 +221,27 @@ hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, 
     hipLaunchKernelGGL(init_state<float>, dim3(n_items), dim3(block), 0, stream, descs, work);
   else
     hipLaunchKernelGGL(init_state<double>, dim3(n_items), dim3(block), 0, stream, descs, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
+                         hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  if (mixed)
+    hipLaunchKernelGGL(filter_ados<float>, dim3(n_items), dim3(256), 0, stream, descs, work);
+  else
+    hipLaunchKernelGGL(filter_ados<double>, dim3(n_items), dim3(256), 0, stream, descs, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_halo(bool mixed, const InstDesc *descs, const HaloEntry *list, int n,
+                       int stage, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + 255) / 256);
+  if (mixed)
+    hipLaunchKernelGGL(halo_fill<float>, grid, dim3(256), 0, stream, descs, list, n, stage);
+  else
+    hipLaunchKernelGGL(halo_fill<double>, grid, dim3(256), 0, stream, descs, list, n, stage);
   return hipGetLastError();
 }
 

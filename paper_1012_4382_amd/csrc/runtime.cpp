@@ -24,16 +24,21 @@ namespace heom {
 
 // kernels_dispatch.hip
 bool has_fixed_kernel(int N, int KP);
-hipError_t prepare_wide(int N, int M, bool mixed);
+hipError_t prepare_wide(int N, int M, bool mixed, int levels);
+bool has_wide_kernel(int N, int M, bool mixed, int levels);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
-                        int stage, double coef, int hist_slot, bool streaming,
+                        int stage, double coef, int hist_slot, bool streaming, int levels,
                         hipStream_t stream);
+hipError_t launch_filter(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
+                         hipStream_t stream);
 hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, int n_items,
                        int block, hipStream_t stream);
 hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
                            hipStream_t stream);
 hipError_t static_scratch(int device, void **ptr);
+hipError_t launch_halo(bool mixed, const InstDesc *descs, const HaloEntry *list, int n,
+                       int stage, hipStream_t stream);
 
 namespace {
 
@@ -85,11 +90,14 @@ struct Layout {
 
 // Work-list entries an instance of n_ados ADOs can need: its stage items in
 // 16-ADO and in 64-ADO tiles (a group may carry both lists), the sigma_0 item
-// of an FP32-mixed tile list, its initialisation items (one per 64 ADOs) and
-// the padding of each list to a multiple of the XCD count.
+// of an FP32-mixed tile list, its initialisation and filter items (one per 64
+// ADOs each) and the padding of each list to a multiple of the XCD count.
 int64_t work_items_cap(int64_t n_ados) {
-  return (n_ados + 15) / 16 + 2 * ((n_ados + kPlanePad - 1) / kPlanePad) + 16;
+  return (n_ados + 15) / 16 + 3 * ((n_ados + kPlanePad - 1) / kPlanePad) + 16;
 }
+
+// Occupations per mode in the weight tables of a scaled hierarchy (0: not scaled).
+int weight_levels(const heom_hierarchy *h) { return h->scaled ? h->depth + 1 : 0; }
 
 Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   Layout L;
@@ -110,7 +118,7 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
     const size_t N2 = static_cast<size_t>(h->N) * h->N;
     InstLayout &I = L.inst[k];
     I.params = off;
-    off = align_up(off + sizeof(double) * param_offsets(h->N, h->M).total);
+    off = align_up(off + sizeof(double) * h->params.size());
     const size_t plane_bytes = elt * N2 * static_cast<size_t>(h->stride);
     I.y = off;
     off = align_up(off + plane_bytes);
@@ -323,6 +331,7 @@ struct StepGraph {
 struct Group {
   KernelKind kind;
   int N, KP;
+  int levels = 0;  // scaled hierarchies: weight levels (wide kernel only)
   int shape;    // launch shape (kTile only)
   bool streaming = false;  // non-temporal output stores (kTile only)
   int threads;  // of the chosen shape
@@ -335,8 +344,12 @@ struct Group {
 // for the wide kernel, whose loads use 32-bit byte offsets from the buffer
 // bases, state buffers below 4 GiB.
 bool shape_ok(const heom_hierarchy *h, bool mixed, int s) {
-  if (!tile_shape_info(h->N, h->KP, mixed, s, nullptr, nullptr, nullptr, nullptr, nullptr))
+  if (h->scaled) {  // the wide kernel only, with its weight tables in LDS
+    if (s != kWideShape || !has_wide_kernel(h->N, h->M, mixed, weight_levels(h))) return false;
+  } else if (!tile_shape_info(h->N, h->KP, mixed, s, nullptr, nullptr, nullptr, nullptr,
+                              nullptr)) {
     return false;
+  }
   if (s != kWideShape) return true;
   const uint64_t bytes = static_cast<uint64_t>(h->N) * h->N * h->stride * (mixed ? 4 : 8);
   return bytes < (uint64_t{1} << 32);
@@ -398,10 +411,20 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
   // kernels will run.
   const int forced = forced_shape(flags);
   if (forced >= kMaxTileShapes) return fail(HEOM_E_INVALID, "tile launch shape out of range");
+  const bool mixed = precision == HEOM_FP32_MIXED;
+  for (int k = 0; k < n; ++k)
+    if (hs[k]->scaled) {
+      if (flags & (HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL))
+        return fail(HEOM_E_UNSUPPORTED, "scaled hierarchies run on the LDS-tiled wide kernel only");
+      if (!shape_ok(hs[k], mixed, kWideShape))
+        return fail(HEOM_E_UNSUPPORTED,
+                    "scaled hierarchies need the wide kernel: real H, N <= 32, K + 1 <= 4, "
+                    "its LDS within 160 KB and state buffers below 4 GiB");
+    }
   if (forced >= 0 && !(flags & (HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)))
     for (int k = 0; k < n; ++k) {
       const heom_hierarchy *h = hs[k];
-      const bool mixed = precision == HEOM_FP32_MIXED;
+      if (h->scaled) continue;  // always the wide kernel
       if (h->h_real && has_tiled(h, mixed) && !shape_ok(h, mixed, forced))
         return fail(HEOM_E_UNSUPPORTED, "tile launch shape " + std::to_string(forced) +
                                             " is not built for N=" + std::to_string(h->N) +
@@ -421,6 +444,12 @@ struct RunOptions {
   // tables must already be resident, launch shapes come from the autotuner's
   // cache or the defaults, every launch goes directly to the caller's stream.
   bool no_alloc = false;
+  // The instances are the ranks of one split hierarchy: instances after the
+  // first do not hold sigma_0, and the n_halo entries at d_halo are copied
+  // into each stage's input before the stage runs.
+  bool shard = false;
+  const HaloEntry *d_halo = nullptr;
+  int n_halo = 0;
 };
 
 int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const int32_t *start,
@@ -482,13 +511,18 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     d.N = hs[k]->N;
     d.M = hs[k]->M;
     d.KP = hs[k]->KP;
+    d.flags = ((opt.shard && k > 0) ? kInstNoSigma0 : 0) | (hs[k]->scaled ? kInstScaled : 0);
+    d.levels = weight_levels(hs[k]);
     d.pad_ = 0;
+    d.filter_tol = hs[k]->filter_tol;
   }
-  std::map<std::tuple<int, int, int>, std::vector<int>> by_key;
+  std::map<std::tuple<int, int, int, int>, std::vector<int>> by_key;
   for (int k = 0; k < n; ++k) {
     const heom_hierarchy *h = hs[k];
     KernelKind kind = KernelKind::kGeneric;
-    if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real) {
+    if (h->scaled) {
+      kind = KernelKind::kTile;  // validated by check_common: the wide kernel
+    } else if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real) {
       if (flags & HEOM_LANE_KERNEL) {
         if (has_fixed_kernel(h->N, h->KP)) kind = KernelKind::kLane;
       } else if (has_tiled(h, mixed)) {
@@ -496,7 +530,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       }
     }
     const int kp = (kind == KernelKind::kGeneric) ? 0 : h->KP;
-    by_key[std::make_tuple(static_cast<int>(kind), h->N, kp)].push_back(k);
+    by_key[std::make_tuple(static_cast<int>(kind), h->N, kp, weight_levels(h))].push_back(k);
   }
   std::vector<WorkItem> items;
   std::vector<Group> groups;
@@ -533,6 +567,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     g.kind = static_cast<KernelKind>(std::get<0>(kv.first));
     g.N = std::get<1>(kv.first);
     g.KP = std::get<2>(kv.first);
+    g.levels = std::get<3>(kv.first);
     g.shape = 0;
     g.n_tiles = 0;
     for (int k : kv.second) g.n_tiles += (hs[k]->n_ados + kPlanePad - 1) / kPlanePad;
@@ -545,7 +580,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       if (tile) add_list(kv.second, kPlanePad, mixed, &g.begin[0], &g.count[0]);
       if (wide) {
         add_list(kv.second, 16, false, &g.begin[1], &g.count[1]);
-        HEOM_HIP(prepare_wide(g.N, g.N * g.KP, mixed), "wide kernel attributes");
+        HEOM_HIP(prepare_wide(g.N, g.N * g.KP, mixed, g.levels), "wide kernel attributes");
       }
       g.shape = tile ? 0 : kWideShape;
       tile_shape_info(g.N, g.KP, mixed, g.shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
@@ -562,6 +597,13 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       for (int64_t first = 0; first < hs[k]->n_ados; first += kPlanePad)
         items.push_back({k, static_cast<int32_t>(first)});
   const int64_t n_init = static_cast<int64_t>(items.size()) - init_begin;
+  // Filter items (64 ADOs each) of the instances with a filter.
+  const int64_t filter_begin = static_cast<int64_t>(items.size());
+  for (int k = 0; k < n; ++k)
+    if (hs[k]->filter_tol > 0.0)
+      for (int64_t first = 0; first < hs[k]->n_ados; first += kPlanePad)
+        items.push_back({k, static_cast<int32_t>(first)});
+  const int64_t n_filter = static_cast<int64_t>(items.size()) - filter_begin;
   if (static_cast<int64_t>(items.size()) > place.work_cap)
     return fail(HEOM_E_WORKSPACE, "work list exceeds its workspace region");
 
@@ -645,7 +687,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   // buffers they leave behind before reading them, so the run is unchanged.
   for (Group &g : groups) {
     if (g.kind != KernelKind::kTile) continue;
-    int shape = forced_shape(flags);  // validated by check_common
+    int shape = g.levels > 0 ? kWideShape : forced_shape(flags);  // validated by check_common
     bool streaming = false;
     if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = g.shape;
     if (shape < 0 && opt.no_alloc) {
@@ -675,7 +717,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
             if (e == hipSuccess)
               e = launch_stage(g.kind, mixed, g.N, g.KP, s, d_descs, d_work + g.begin[l],
                                static_cast<int>(g.count[l]), threads, st, coef[st], -1, nt,
-                               stream);
+                               g.levels, stream);
           return e;
         };
         hipError_t e = hipEventCreate(&ev[0]);
@@ -717,11 +759,12 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     const int l = g.list(g.shape);
     return launch_stage(g.kind, mixed, g.N, g.KP, g.shape, d_descs, d_work + g.begin[l],
                         static_cast<int>(g.count[l]), g.threads, st, coef[st], -1, g.streaming,
-                        s);
+                        g.levels, s);
   };
   auto enqueue_step = [&](hipStream_t s) -> hipError_t {
     for (int st = 0; st < 4; ++st) {
-      hipError_t e = hipSuccess;
+      hipError_t e = launch_halo(mixed, d_descs, opt.d_halo, opt.n_halo, st, s);
+      if (e != hipSuccess) return e;
       if (!fj) {
         for (const Group &g : groups)
           if (e == hipSuccess) e = launch_group(g, st, s);
@@ -739,7 +782,8 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
         e = hipStreamWaitEvent(s, fj->join[gi], 0);
       if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    // The filter of scaled hierarchies, on the state the step produced.
+    return launch_filter(mixed, d_descs, d_work + filter_begin, static_cast<int>(n_filter), s);
   };
   // Runs of kGraphSteps steps are replayed from one captured graph, which
   // removes the host launch cost of each stage kernel.
@@ -975,6 +1019,45 @@ int heom_build_hierarchy(const heom_system *sys, int32_t depth, heom_hierarchy *
   return HEOM_OK;
 }
 
+int heom_build_hierarchy_scaled(const heom_system *sys, int32_t depth, double filter_tol,
+                                heom_hierarchy **out) {
+  if (!out) return fail(HEOM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!(filter_tol >= 0.0) || !std::isfinite(filter_tol))
+    return fail(HEOM_E_INVALID, "filter_tol must be finite and >= 0");
+  heom_hierarchy *h = nullptr;
+  int rc = heom_build_hierarchy(sys, depth, &h);
+  if (rc) return rc;
+  // Coupling weights by mode and occupation: the ADO n is held divided by
+  // w_n = sqrt(prod_m n_m! |c_m|^n_m), so the coupling to n + e_m carries
+  // w_{n+e_m} / w_n = sqrt((n_m + 1)|c_m|) and the one to n - e_m carries
+  // n_m w_{n-e_m} / w_n = sqrt(n_m / |c_m|).
+  const int M = h->M, L = depth + 1;
+  for (int m = 0; m < M; ++m)
+    if (!(std::hypot(h->c_re[m], h->c_im[m]) > 0.0)) {
+      heom_destroy(h);
+      return fail(HEOM_E_INVALID, "a scaled hierarchy needs nonzero bath amplitudes (lambda > 0)");
+    }
+  try {
+    const size_t base = h->params.size();
+    h->params.resize(base + 2 * static_cast<size_t>(M) * L);
+    for (int m = 0; m < M; ++m) {
+      const double absc = std::hypot(h->c_re[m], h->c_im[m]);
+      for (int v = 0; v < L; ++v) {
+        h->params[base + m * L + v] = std::sqrt((v + 1.0) * absc);
+        h->params[base + M * L + m * L + v] = std::sqrt(v / absc);
+      }
+    }
+  } catch (...) {
+    heom_destroy(h);
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+  h->scaled = true;
+  h->filter_tol = filter_tol;
+  *out = h;
+  return HEOM_OK;
+}
+
 int heom_hierarchy_info(const heom_hierarchy *h, int64_t *n_ados, int32_t *n_modes,
                         size_t *workspace_bytes_fp64, size_t *workspace_bytes_fp32) {
   if (!h) return fail(HEOM_E_INVALID, "hierarchy is NULL");
@@ -1197,6 +1280,172 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
   tail[1] = sc[1];
   tail[2] = sc[2];
   return HEOM_OK;
+}
+
+// --- a hierarchy split over ranks (its one-GPU part) -------------------------
+
+int heom_shard_build(const heom_hierarchy *h, int32_t n_ranks, heom_shard **out) {
+  if (!h || !out) return fail(HEOM_E_INVALID, "hierarchy or out is NULL");
+  *out = nullptr;
+  if (h->scaled) return fail(HEOM_E_UNSUPPORTED, "scaled hierarchies are not split over ranks");
+  heom_shard *s = new (std::nothrow) heom_shard();
+  if (!s) return fail(HEOM_E_NOMEM, "host allocation failed");
+  int rc = HEOM_OK;
+  try {
+    rc = build_shard(h, n_ranks, s);
+  } catch (...) {
+    rc = fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+  if (rc != HEOM_OK) {
+    heom_shard_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return HEOM_OK;
+}
+
+int heom_shard_info(const heom_shard *s, int32_t rank, heom_shard_rank_info *out) {
+  if (!s || !out) return fail(HEOM_E_INVALID, "shard or out is NULL");
+  if (rank < 0 || rank >= s->n_ranks) return fail(HEOM_E_INVALID, "rank out of range");
+  const heom_shard::Stats &st = s->stats[rank];
+  out->first_ado = s->first[rank];
+  out->n_local = s->first[rank + 1] - s->first[rank];
+  out->n_halo = st.n_halo;
+  out->cut_links = st.cut_links;
+  out->halo_reals = st.n_halo * static_cast<int64_t>(s->N) * s->N;
+  out->halo_reals_min = st.halo_reals_min;
+  return HEOM_OK;
+}
+
+namespace {
+
+// Workspace of a split hierarchy: every rank laid out as an instance of a
+// batch, then the halo list.
+struct ShardLayout {
+  Layout L;
+  size_t halo = 0, total = 0;
+};
+ShardLayout shard_layout(const heom_shard *s, int precision) {
+  ShardLayout S;
+  S.L = make_layout(s->rank.data(), s->n_ranks, precision);
+  S.halo = S.L.total;
+  S.total = align_up(S.halo + sizeof(HaloEntry) * s->halo.size());
+  return S;
+}
+
+}  // namespace
+
+int heom_shard_workspace_bytes(const heom_shard *s, int precision, size_t *bytes) {
+  if (!s || !bytes) return fail(HEOM_E_INVALID, "shard or bytes is NULL");
+  if (precision != HEOM_FP64) return fail(HEOM_E_UNSUPPORTED, "split hierarchies run in FP64");
+  *bytes = shard_layout(s, precision).total;
+  return HEOM_OK;
+}
+
+int heom_propagate_sharded(heom_shard *s, int precision, int flags, const double *rho0,
+                           double dt_fs, int64_t n_steps, int64_t record_every, void *d_workspace,
+                           size_t workspace_bytes, void *hip_stream, double *rho_out,
+                           double *sinks_out) {
+  try {
+    if (!s) return fail(HEOM_E_INVALID, "shard is NULL");
+    if (precision != HEOM_FP64) return fail(HEOM_E_UNSUPPORTED, "split hierarchies run in FP64");
+    const int n = s->n_ranks;
+    heom_hierarchy *const *hs = s->rank.data();
+    int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, record_every,
+                          HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
+                              HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
+                              kShapeFlagMask);
+    if (rc) return rc;
+    const ShardLayout S = shard_layout(s, precision);
+    if (!d_workspace) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+      return fail(HEOM_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < S.total)
+      return fail(HEOM_E_WORKSPACE,
+                  "workspace too small: need " + std::to_string(S.total) + " bytes");
+    char *ws = static_cast<char *>(d_workspace);
+    RunPlace P;
+    P.base.assign(n, ws);
+    P.inst = S.L.inst;
+    P.header = {ws + S.L.header};
+    P.want = {header_for(hs, n, precision)};
+    P.header_of.assign(n, 0);
+    P.descs = ws + S.L.descs;
+    P.work = ws + S.L.work;
+    P.work_cap = S.L.work_cap;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (!s->halo.empty())
+      HEOM_HIP(hipMemcpyAsync(ws + S.halo, s->halo.data(), sizeof(HaloEntry) * s->halo.size(),
+                              hipMemcpyHostToDevice, stream),
+               "hipMemcpyAsync(halo list)");
+    const std::vector<int32_t> start(n, (flags & HEOM_RESUME) ? 0 : 1);
+    const std::vector<const double *> rho0s(n, rho0);
+    std::vector<double *> ro(n, nullptr), so(n, nullptr);
+    ro[0] = rho_out;
+    so[0] = sinks_out;
+    RunOptions opt;
+    opt.shard = true;
+    opt.d_halo = reinterpret_cast<const HaloEntry *>(ws + S.halo);
+    opt.n_halo = static_cast<int>(s->halo.size());
+    return run_impl(hs, n, precision, flags & ~HEOM_RESUME, start.data(), rho0s.data(), dt_fs,
+                    n_steps, record_every, P, hip_stream, ro.data(), so.data(), opt);
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+}
+
+int heom_read_state_sharded(const heom_shard *s, int precision, const void *d_workspace,
+                            size_t workspace_bytes, void *hip_stream, double *state_out) {
+  if (!s || !state_out) return fail(HEOM_E_INVALID, "shard or state_out is NULL");
+  if (precision != HEOM_FP64) return fail(HEOM_E_UNSUPPORTED, "split hierarchies run in FP64");
+  const ShardLayout S = shard_layout(s, precision);
+  if (!d_workspace || workspace_bytes < S.total)
+    return fail(HEOM_E_WORKSPACE, "workspace missing or too small");
+  const char *ws = static_cast<const char *>(d_workspace);
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const int N = s->N;
+  const size_t N2 = static_cast<size_t>(N) * N;
+  Header cur;
+  std::vector<double> sc(kScalars);
+  std::vector<std::vector<double>> planes(s->n_ranks);
+  try {
+    for (int r = 0; r < s->n_ranks; ++r) planes[r].resize(N2 * s->rank[r]->stride);
+  } catch (...) {
+    return fail(HEOM_E_NOMEM, "host allocation failed");
+  }
+  HEOM_HIP(hipMemcpyAsync(&cur, ws + S.L.header, sizeof(Header), hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync(header)");
+  for (int r = 0; r < s->n_ranks; ++r)
+    HEOM_HIP(hipMemcpyAsync(planes[r].data(), ws + S.L.inst[r].y,
+                            sizeof(double) * planes[r].size(), hipMemcpyDeviceToHost, stream),
+             "hipMemcpyAsync(state)");
+  HEOM_HIP(hipMemcpyAsync(sc.data(), ws + S.L.inst[0].sc_y, sizeof(double) * kScalars,
+                          hipMemcpyDeviceToHost, stream),
+           "hipMemcpyAsync(scalars)");
+  HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  heom_hierarchy *const *hs = s->rank.data();
+  const Header want = header_for(hs, s->n_ranks, precision);
+  if (std::memcmp(&cur, &want, sizeof(Header)) != 0)
+    return fail(HEOM_E_WORKSPACE, "workspace does not hold a run of this split hierarchy");
+  std::vector<double> packed(N2);
+  for (int r = 0; r < s->n_ranks; ++r) {
+    const heom_hierarchy *g = s->rank[r];
+    for (int64_t li = 0; li < g->n_ados; ++li) {
+      for (size_t e = 0; e < N2; ++e) packed[e] = planes[r][e * g->stride + li];
+      unpack_hermitian(N, packed.data(), state_out + 2 * N2 * (s->first[r] + li));
+    }
+  }
+  double *tail = state_out + 2 * N2 * s->n_ados;
+  tail[0] = sc[0];
+  tail[1] = sc[1];
+  tail[2] = sc[2];
+  return HEOM_OK;
+}
+
+void heom_shard_destroy(heom_shard *s) {
+  if (!s) return;
+  for (heom_hierarchy *h : s->rank) heom_destroy(h);
+  delete s;
 }
 
 int heom_tile_shape_count(void) { return kMaxTileShapes; }

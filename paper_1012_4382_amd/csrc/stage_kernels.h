@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(256) stage_fixed(const InstDesc *__restrict__ 
   const int64_t i = static_cast<int64_t>(w.first) + threadIdx.x;
   if (i >= d.n_ados) return;
   constexpr bool MIXED = sizeof(T) == 4;
-  if (i == 0)
+  if (i == 0 && !(d.flags & kInstNoSigma0))
     update_fixed<N, KP, double, T, MIXED, true>(d, i, stage, coef, hist_slot);
   else
     update_fixed<N, KP, T, T, MIXED, false>(d, i, stage, coef, hist_slot);
@@ -553,7 +553,7 @@ __global__ void __launch_bounds__(256) stage_generic(const InstDesc *__restrict_
   const int64_t i = static_cast<int64_t>(w.first) + threadIdx.x;
   if (i >= d.n_ados) return;
   constexpr bool MIXED = sizeof(T) == 4;
-  if (i == 0)
+  if (i == 0 && !(d.flags & kInstNoSigma0))
     update_generic<double, T, MIXED, true>(d, i, stage, coef, hist_slot);
   else
     update_generic<T, T, MIXED, false>(d, i, stage, coef, hist_slot);
@@ -1064,7 +1064,7 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   // this in the sigma_0 item): wave 0 of the first tile, every lane still
   // active.
   if constexpr (!MIXED) {
-    if (w.first == 0 && wave == 0)
+    if (w.first == 0 && wave == 0 && !(d.flags & kInstNoSigma0))
       scalar_update_wave(d, bufs, N, coef, lane, [&](int q) { return sx[q * kTile]; });
   }
   const HEOM_CONST double *P = cmem(d.params);
@@ -1140,11 +1140,12 @@ struct WideEntry {
 };
 
 // LDS layout of the wide kernel (byte offsets; every region 16-byte aligned).
+// `levels` > 0 (scaled hierarchies) adds the coupling-weight tables.
 struct WideLds {
-  int x, ent, nz, dec, dl, cr, ci, nu, up, dn, occ, pa, pb, x0, total;
+  int x, ent, nz, dec, dl, cr, ci, nu, up, dn, occ, pa, pb, x0, wu, wd, total;
 };
 __host__ __device__ inline int wide_align(int v) { return (v + 15) & ~15; }
-__host__ __device__ inline WideLds wide_lds(int N, int M, int s) {
+__host__ __device__ inline WideLds wide_lds(int N, int M, int s, int levels = 0) {
   const int P = N * (N + 1) / 2;
   WideLds L;
   L.x = 0;                                                    // T [N*N + 1][kWideAdos]
@@ -1161,7 +1162,9 @@ __host__ __device__ inline WideLds wide_lds(int N, int M, int s) {
   L.pa = wide_align(L.occ + M * kWideAdos);                   // uint8 [P] element -> a
   L.pb = wide_align(L.pa + P);                                // uint8 [P] element -> b
   L.x0 = wide_align(L.pb + P);                                // double [N*N] (FP32 storage)
-  L.total = wide_align(L.x0 + (s == 4 ? N * N * 8 : 0));
+  L.wu = wide_align(L.x0 + (s == 4 ? N * N * 8 : 0));         // double [M][levels] (scaled)
+  L.wd = wide_align(L.wu + M * levels * 8);                   // double [M][levels] (scaled)
+  L.total = wide_align(L.wd + M * levels * 8);
   return L;
 }
 
@@ -1182,6 +1185,8 @@ struct WideCtx {
   uint32_t S;  // plane stride in ADOs; every buffer of a wide launch is below 4 GiB
   int64_t i;
   double damp, coef;
+  const double *swu, *swd;  // scaled hierarchies: coupling weights [M][levels] (LDS)
+  int levels;
 };
 
 // Global values one element needs: neighbour gathers along the modes of its
@@ -1246,8 +1251,11 @@ __device__ __forceinline__ void wide_load(const WideCtx<T> &c, int a, int b,
 // Phase 2 of element (a, b) (tile_finish with runtime a, b): the commutator
 // from LDS over the nonzero couplings in increasing k (negating an imaginary
 // part equals the tile kernel's multiplication by -1), then decay, bath
-// couplings, RK4 stage and store, in the tile kernel's order.
-template <typename C, typename T, bool X0SRC, int KP>
+// couplings, RK4 stage and store, in the tile kernel's order.  SCALED: the
+// hierarchy holds sigma_n / w_n, so the coupling to n + e_m is weighted by
+// sqrt((n_m + 1)|c_m|) instead of 1 and the one to n - e_m by sqrt(n_m / |c_m|)
+// instead of n_m (weights from the host, by mode and occupation).
+template <typename C, typename T, bool X0SRC, int KP, bool SCALED>
 __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
                                             const WideLoads<C, KP> &L) {
 #pragma clang fp contract(off)
@@ -1294,16 +1302,24 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int ma = a * KP + k, mb = b * KP + k;
+    const int oa = c.socc[ma * kWideAdos + t], ob = c.socc[mb * kWideAdos + t];
     if (offd) {
-      const C fa = L.jua[k] >= 0 ? C(1) : C(0);
-      const C fb = L.jub[k] >= 0 ? C(1) : C(0);
+      C fa = L.jua[k] >= 0 ? C(1) : C(0);
+      C fb = L.jub[k] >= 0 ? C(1) : C(0);
+      if constexpr (SCALED) {
+        fa = L.jua[k] >= 0 ? static_cast<C>(c.swu[ma * c.levels + oa]) : C(0);
+        fb = L.jub[k] >= 0 ? static_cast<C>(c.swu[mb * c.levels + ob]) : C(0);
+      }
       ar = fmad(-fa, L.yai[k], fmad(fb, L.ybi[k], ar));
       ai = fmad(-fb, L.ybr[k], fmad(fa, L.yar[k], ai));
     }
     const C za_i = offd ? L.zai[k] : C(0);
     const C zb_i = offd ? L.zbi[k] : C(0);
-    const C na = static_cast<C>(c.socc[ma * kWideAdos + t]);
-    const C nb = static_cast<C>(c.socc[mb * kWideAdos + t]);
+    C na = static_cast<C>(oa), nb = static_cast<C>(ob);
+    if constexpr (SCALED) {
+      na = static_cast<C>(c.swd[ma * c.levels + oa]);
+      nb = static_cast<C>(c.swd[mb * c.levels + ob]);
+    }
     const C car = na * static_cast<C>(c.scr[ma]), cai = na * static_cast<C>(c.sci[ma]);
     const C cbr = nb * static_cast<C>(c.scr[mb]), cbi = nb * static_cast<C>(c.sci[mb]);
     ar = fmad(-car, za_i, fmad(-cai, L.zar[k], ar));
@@ -1325,7 +1341,7 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
   if (offd) st_off<false>(c.Out, static_cast<uint32_t>(E + 1) * c.S * sz + oi, static_cast<T>(ni));
 }
 
-template <typename T, int KP>
+template <typename T, int KP, bool SCALED>
 __global__ void __launch_bounds__(64 * kWideWaves)
     stage_wide(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
                double coef, int /*hist_slot: recorded by the snapshot kernel*/) {
@@ -1334,7 +1350,8 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   const WorkItem w = work[blockIdx.x];
   const InstDesc &d = descs[w.inst];
   const int N = d.N, M = d.M, N2 = N * N, P = N * (N + 1) / 2;
-  const WideLds L = wide_lds(N, M, static_cast<int>(sizeof(T)));
+  const int levels = SCALED ? d.levels : 0;
+  const WideLds L = wide_lds(N, M, static_cast<int>(sizeof(T)), levels);
   T *sx = reinterpret_cast<T *>(wide_smem + L.x);
   WideEntry *sent = reinterpret_cast<WideEntry *>(wide_smem + L.ent);
   uint32_t *snz = reinterpret_cast<uint32_t *>(wide_smem + L.nz);
@@ -1349,6 +1366,8 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   uint8_t *spa = reinterpret_cast<uint8_t *>(wide_smem + L.pa);
   uint8_t *spb = reinterpret_cast<uint8_t *>(wide_smem + L.pb);
   double *sx0 = reinterpret_cast<double *>(wide_smem + L.x0);
+  double *swu = reinterpret_cast<double *>(wide_smem + L.wu);
+  double *swd = reinterpret_cast<double *>(wide_smem + L.wd);
 
   const StageBufs bufs = stage_bufs(d, stage);
   const int64_t S = d.stride;
@@ -1399,13 +1418,17 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     spa[p] = static_cast<uint8_t>(elem_a(N, p));
     spb[p] = static_cast<uint8_t>(elem_b(N, p));
   }
+  for (int idx = tid; idx < M * levels; idx += blockDim.x) {  // scaled only
+    swu[idx] = Pg[o.total + idx];
+    swd[idx] = Pg[o.total + M * levels + idx];
+  }
   if constexpr (MIXED) {
     if (w.first == 0)
       for (int e = tid; e < N2; e += blockDim.x) sx0[e] = bufs.x0[e];
   }
   __syncthreads();
   // Sink fluxes and scalars of sigma_0: wave 0 of the first tile.
-  if (w.first == 0 && tid < 64) {
+  if (w.first == 0 && tid < 64 && !(d.flags & kInstNoSigma0)) {
     scalar_update_wave(d, bufs, N, coef, tid, [&](int e) {
       if constexpr (MIXED)
         return sx0[e];
@@ -1443,7 +1466,10 @@ __global__ void __launch_bounds__(64 * kWideWaves)
                       static_cast<uint32_t>(S),
                       ii,
                       damp,
-                      coef};
+                      coef,
+                      swu,
+                      swd,
+                      levels};
   };
   // With FP32 storage, sigma_0 is computed separately below, in FP64.
   if (i < d.n_ados && !(MIXED && i == 0)) {
@@ -1451,7 +1477,7 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     for (int p = slot; p < P; p += kWideSlots) {
       WideLoads<T, KP> Ld;
       wide_load<T, T, false, KP>(ctx, spa[p], spb[p], Ld);
-      wide_finish<T, T, false, KP>(ctx, spa[p], spb[p], Ld);
+      wide_finish<T, T, false, KP, SCALED>(ctx, spa[p], spb[p], Ld);
     }
   }
   if constexpr (MIXED) {
@@ -1462,7 +1488,7 @@ __global__ void __launch_bounds__(64 * kWideWaves)
       for (int p = tid; p < P; p += blockDim.x) {
         WideLoads<double, KP> L0;
         wide_load<double, T, true, KP>(ctx0, spa[p], spb[p], L0);
-        wide_finish<double, T, true, KP>(ctx0, spa[p], spb[p], L0);
+        wide_finish<double, T, true, KP, SCALED>(ctx0, spa[p], spb[p], L0);
       }
     }
   }
@@ -1484,12 +1510,59 @@ __global__ void __launch_bounds__(256) init_state(const InstDesc *__restrict__ d
   const int N2 = d.N * d.N;
   const ParamOffsets o = param_offsets(d.N, d.M);
   T *y = static_cast<T *>(d.y);
-  for (int e = 0; e < N2; ++e) y[e * d.stride + i] = (i == 0) ? static_cast<T>(d.params[o.rho0 + e]) : T(0);
-  if (i == 0) {
+  const bool s0 = i == 0 && !(d.flags & kInstNoSigma0);
+  for (int e = 0; e < N2; ++e) y[e * d.stride + i] = s0 ? static_cast<T>(d.params[o.rho0 + e]) : T(0);
+  if (s0) {
     if (sizeof(T) == 4)
       for (int e = 0; e < N2; ++e) d.y0[e] = d.params[o.rho0 + e];
     for (int k = 0; k < kScalars; ++k) d.sc_y[k] = 0.0;
   }
+}
+
+// Copies the halo ADOs of split hierarchies into the input buffer of `stage`
+// (one lane per halo ADO, a loop over the rows and columns of its linking
+// sites): on one GPU this stands in for the point-to-point exchange between
+// the ranks that hold the shares.
+template <typename T>
+__global__ void __launch_bounds__(256) halo_fill(const InstDesc *__restrict__ descs,
+                                                 const HaloEntry *__restrict__ list, int n,
+                                                 int stage) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const HaloEntry h = list[q];
+  const InstDesc &dd = descs[h.dst];
+  const InstDesc &ds = descs[h.src];
+  const T *src = static_cast<const T *>(stage_bufs(ds, stage).x);
+  T *dst = static_cast<T *>(const_cast<void *>(stage_bufs(dd, stage).x));
+  const int N = dd.N;
+  auto copy = [&](int e) { dst[e * dd.stride + h.dst_index] = src[e * ds.stride + h.src_index]; };
+  for (int a = 0; a < N; ++a) {
+    const bool in_a = (h.sites >> a) & 1;
+    if (in_a) copy(a);
+    for (int b = a + 1; b < N; ++b)
+      if (in_a || ((h.sites >> b) & 1)) {
+        copy(re_plane(N, a, b));
+        copy(re_plane(N, a, b) + 1);
+      }
+  }
+}
+
+// The filter of a scaled hierarchy, after the last stage of a step: every ADO
+// n != 0 (one lane each) whose stored reals are all below the instance's
+// threshold in absolute value is set to zero in the state.
+template <typename T>
+__global__ void __launch_bounds__(256) filter_ados(const InstDesc *__restrict__ descs,
+                                                   const WorkItem *__restrict__ work) {
+  const WorkItem w = work[blockIdx.x];
+  const InstDesc &d = descs[w.inst];
+  const int64_t i = static_cast<int64_t>(w.first) + threadIdx.x;
+  if (i >= d.n_ados || (i == 0 && !(d.flags & kInstNoSigma0))) return;
+  T *y = static_cast<T *>(d.y);
+  const int N2 = d.N * d.N;
+  double mx = 0.0;
+  for (int e = 0; e < N2; ++e) mx = fmax(mx, fabs(static_cast<double>(y[e * d.stride + i])));
+  if (mx < d.filter_tol)
+    for (int e = 0; e < N2; ++e) y[e * d.stride + i] = T(0);
 }
 
 // Writes the current sigma_0 and scalars of each instance to history slot.

@@ -87,6 +87,12 @@ class _System(ctypes.Structure):
     ]
 
 
+class ShardRankInfo(ctypes.Structure):
+    _fields_ = [("first_ado", ctypes.c_int64), ("n_local", ctypes.c_int64),
+                ("n_halo", ctypes.c_int64), ("cut_links", ctypes.c_int64),
+                ("halo_reals", ctypes.c_int64), ("halo_reals_min", ctypes.c_int64)]
+
+
 class EffResult(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("mean_trap_time_fs", ctypes.c_double),
                 ("p_recomb", ctypes.c_double), ("p_remaining", ctypes.c_double),
@@ -101,6 +107,7 @@ _d, _i32, _i64, _sz, _vp = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctyp
     ctypes.c_void_p
 _SIGNATURES = [
     ("heom_build_hierarchy", ctypes.c_int, [_P(_System), _i32, _P(ctypes.c_void_p)]),
+    ("heom_build_hierarchy_scaled", ctypes.c_int, [_P(_System), _i32, _d, _P(ctypes.c_void_p)]),
     ("heom_hierarchy_info", ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_sz), _P(_sz)]),
     ("heom_hierarchy_tables", ctypes.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32)]),
     ("heom_hierarchy_modes", ctypes.c_int, [_vp, _P(_i32), _P(_d), _P(_d), _P(_d), _P(_d)]),
@@ -120,6 +127,13 @@ _SIGNATURES = [
     ("heom_advance_slots_noalloc", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, ctypes.c_int,
                                                   _P(_vp), _P(_sz), _P(_i32), _P(_P(_d)), _d,
                                                   _i64, _vp, _P(_P(_d)), _P(_P(_d))]),
+    ("heom_shard_build", ctypes.c_int, [_vp, _i32, _P(ctypes.c_void_p)]),
+    ("heom_shard_info", ctypes.c_int, [_vp, _i32, _P(ShardRankInfo)]),
+    ("heom_shard_workspace_bytes", ctypes.c_int, [_vp, ctypes.c_int, _P(_sz)]),
+    ("heom_propagate_sharded", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _P(_d), _d, _i64,
+                                              _i64, _vp, _sz, _vp, _P(_d), _P(_d)]),
+    ("heom_read_state_sharded", ctypes.c_int, [_vp, ctypes.c_int, _vp, _sz, _vp, _P(_d)]),
+    ("heom_shard_destroy", None, [_vp]),
     ("heom_tile_shape_count", ctypes.c_int, []),
     ("heom_tile_shape_info", ctypes.c_int, [_i32, _i32, ctypes.c_int, _i32, _P(_i32), _P(_i32),
                                             _P(_i32), _P(_i32), _P(_i32)]),
@@ -178,9 +192,11 @@ class Hierarchy:
     ``sys`` keys: H (N x N, cm^-1, real or complex Hermitian), lam (cm^-1, scalar
     or (N,)), gamma_inv_fs (fs, scalar or (N,)), T (K), K (Matsubara terms),
     ltc (0/1), theta_form (0/1), trap_per_ps and rec_per_ps ((N,) or None).
+    scaled=True builds the scaled hierarchy (heom_build_hierarchy_scaled), with
+    the filter threshold filter_tol (0: no filter).
     """
 
-    def __init__(self, sys: dict, depth: int):
+    def __init__(self, sys: dict, depth: int, scaled: bool = False, filter_tol: float = 0.0):
         H = np.ascontiguousarray(np.asarray(sys["H"], np.complex128))
         N = H.shape[0]
         self.N = N
@@ -199,8 +215,14 @@ class Hierarchy:
                      int(sys.get("K", 0)), int(sys.get("ltc", 1)), int(sys.get("theta_form", 0)),
                      _dp(keep["tr"]), _dp(keep["rc"]))
         h = ctypes.c_void_p()
-        _check(library().heom_build_hierarchy(ctypes.byref(cs), self.depth, ctypes.byref(h)),
-               "heom_build_hierarchy")
+        self.scaled, self.filter_tol = bool(scaled), float(filter_tol)
+        if self.scaled:
+            _check(library().heom_build_hierarchy_scaled(ctypes.byref(cs), self.depth,
+                                                         self.filter_tol, ctypes.byref(h)),
+                   "heom_build_hierarchy_scaled")
+        else:
+            _check(library().heom_build_hierarchy(ctypes.byref(cs), self.depth, ctypes.byref(h)),
+                   "heom_build_hierarchy")
         self._h = h
         n, m, b64, b32 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_size_t()
         _check(library().heom_hierarchy_info(h, ctypes.byref(n), ctypes.byref(m),
@@ -426,6 +448,76 @@ def advance_slots_noalloc(hs, workspaces, start, rho0s, dt_fs: float, n_steps: i
                                                   _stream_handle(stream), a["ro"], a["so"])
     _slots_status(status, "heom_advance_slots_noalloc", rhos, sinks)
     return rhos, sinks
+
+
+class Shard:
+    """A hierarchy split over n_ranks ranks (heom_shard_build); owns the handle."""
+
+    def __init__(self, h: Hierarchy, n_ranks: int):
+        s = ctypes.c_void_p()
+        _check(library().heom_shard_build(h.handle, int(n_ranks), ctypes.byref(s)),
+               "heom_shard_build")
+        self._s = s
+        self.h = h
+        self.n_ranks = int(n_ranks)
+        b = ctypes.c_size_t()
+        _check(library().heom_shard_workspace_bytes(s, HEOM_FP64, ctypes.byref(b)),
+               "heom_shard_workspace_bytes")
+        self.workspace_bytes = b.value
+
+    @property
+    def handle(self):
+        return self._s
+
+    def info(self, rank: int) -> dict:
+        out = ShardRankInfo()
+        _check(library().heom_shard_info(self._s, int(rank), ctypes.byref(out)),
+               "heom_shard_info")
+        return {f: getattr(out, f) for f, _ in ShardRankInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            library().heom_shard_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def propagate_sharded(s: Shard, rho0, dt_fs: float, n_steps: int, record_every: int = 1,
+                      workspace=None, stream=None, resume: bool = False, kernel: str = "auto",
+                      graphs: bool = True, tile_shape=None, autotune: bool = True, stores=None):
+    """Runs heom_propagate_sharded (FP64).  Returns (rho [records, N, N], sinks [3], workspace)."""
+    if workspace is None:
+        workspace = allocate_workspace(s.workspace_bytes)
+    ptr, nbytes = _ws_args(workspace)
+    flags = _flags(resume, kernel, graphs, tile_shape, autotune, stores)
+    r0 = None
+    if rho0 is not None:
+        r0 = np.ascontiguousarray(np.asarray(rho0, np.complex128)).view(np.float64)
+    N = s.h.N
+    rho = np.zeros((n_steps // record_every + 1, N, N), np.complex128)
+    sinks = np.zeros(3)
+    _check(library().heom_propagate_sharded(s.handle, HEOM_FP64, flags, _dp(r0), float(dt_fs),
+                                            int(n_steps), int(record_every), ptr, nbytes,
+                                            _stream_handle(stream), _dp(rho.view(np.float64)),
+                                            _dp(sinks)), "heom_propagate_sharded")
+    return rho, sinks, workspace
+
+
+def read_state_sharded(s: Shard, workspace, stream=None):
+    """(sigma [n_ados, N, N] complex in the hierarchy's order, scalars [3])."""
+    ptr, nbytes = _ws_args(workspace)
+    h = s.h
+    buf = np.zeros(2 * h.n_ados * h.N * h.N + 3)
+    _check(library().heom_read_state_sharded(s.handle, HEOM_FP64, ptr, nbytes,
+                                             _stream_handle(stream), _dp(buf)),
+           "heom_read_state_sharded")
+    sig = buf[: 2 * h.n_ados * h.N * h.N].view(np.complex128).reshape(h.n_ados, h.N, h.N)
+    return sig, buf[2 * h.n_ados * h.N * h.N:].copy()
 
 
 def tile_shape_count() -> int:

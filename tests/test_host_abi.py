@@ -222,3 +222,76 @@ def test_tile_shapes_and_forced_shape_validation():
     assert "not built" in lib.heom_last_error().decode()
     assert call(heom.tile_shape_flag(count)) == heom.HEOM_E_INVALID
     assert call(1 << 12) == heom.HEOM_E_INVALID
+
+
+@pytest.mark.parametrize("N,K,D,G", [(7, 0, 8, 8), (7, 1, 4, 3), (3, 0, 12, 5), (7, 0, 16, 8)])
+def test_shard_plan_matches_the_tables(N, K, D, G):
+    """The split of a hierarchy over G ranks: contiguous tile-aligned ranges,
+    and per rank the halo (ADOs of other ranks its ADOs link to), the links
+    that leave the range and the reals a rank needs (rows and columns of the
+    linking sites), recomputed here from the library's global tables."""
+    rng = np.random.default_rng(N + 10 * K + D)
+    H = np.diag(rng.uniform(12200, 12600, N))
+    h = heom.Hierarchy(workloads.system(H, K=K), D)
+    s = heom.Shard(h, G)
+    multi, up, down = h.tables()
+    site = np.repeat(np.arange(N), K + 1)
+    firsts = [s.info(r)["first_ado"] for r in range(G)] + [h.n_ados]
+    assert firsts[0] == 0 and all(f % 64 == 0 for f in firsts[:-1])
+    assert all(a < b for a, b in zip(firsts, firsts[1:]))
+    for r in range(G):
+        lo, hi = firsts[r], firsts[r + 1]
+        inf = s.info(r)
+        links = {}
+        for tab in (up, down):
+            sub = tab[lo:hi]
+            out = (sub >= 0) & ((sub < lo) | (sub >= hi))
+            for i, m in zip(*np.nonzero(out)):
+                links.setdefault(int(sub[i, m]), set()).add(int(site[m]))
+        n_links = sum(int(np.sum((t[lo:hi] >= 0) & ((t[lo:hi] < lo) | (t[lo:hi] >= hi))))
+                      for t in (up, down))
+
+        def reals(k):
+            return k + 2 * (N * (N - 1) // 2 - (N - k) * (N - k - 1) // 2)
+        assert inf["n_local"] == hi - lo
+        assert inf["n_halo"] == len(links)
+        assert inf["cut_links"] == n_links
+        assert inf["halo_reals"] == len(links) * N * N
+        assert inf["halo_reals_min"] == sum(reals(len(v)) for v in links.values())
+    s.close()
+
+
+def test_shard_rejects_bad_requests():
+    h = heom.Hierarchy(workloads.fmo_like(seed=0, depth=2)["system"], 2)  # 36 ADOs
+    with pytest.raises(heom.HeomError) as e:
+        heom.Shard(h, 2)  # fewer than 64 ADOs per rank
+    assert e.value.status == heom.HEOM_E_INVALID
+    h3 = heom.Hierarchy(workloads.fmo_like(seed=0, depth=3)["system"], 3)  # 120 ADOs
+    with pytest.raises(heom.HeomError):
+        heom.Shard(h3, 0)
+    s = heom.Shard(h3, 1)
+    assert s.info(0)["n_halo"] == 0 and s.info(0)["n_local"] == 120
+    lib = heom.library()
+    b = ctypes.c_size_t()
+    assert lib.heom_shard_workspace_bytes(s.handle, heom.HEOM_FP32_MIXED,
+                                          ctypes.byref(b)) == heom.HEOM_E_UNSUPPORTED
+
+
+def test_scaled_hierarchy_build_and_validation():
+    w = workloads.fmo_like(seed=0, depth=3)
+    h = heom.Hierarchy(w["system"], 3, scaled=True, filter_tol=1e-9)
+    plain = heom.Hierarchy(w["system"], 3)
+    assert (h.n_ados, h.n_modes) == (plain.n_ados, plain.n_modes)
+    # The weight tables (2 x M x (depth + 1) doubles) enlarge the parameter block.
+    assert h.workspace_bytes[heom.HEOM_FP64] >= plain.workspace_bytes[heom.HEOM_FP64]
+    for bad in (-1e-9, float("nan"), float("inf")):
+        with pytest.raises(heom.HeomError) as e:
+            heom.Hierarchy(w["system"], 3, scaled=True, filter_tol=bad)
+        assert e.value.status == heom.HEOM_E_INVALID
+    with pytest.raises(heom.HeomError) as e:  # lambda = 0: no scale for the modes
+        heom.Hierarchy(dict(w["system"], lam=0.0), 3, scaled=True)
+    assert e.value.status == heom.HEOM_E_INVALID
+    with pytest.raises(heom.HeomError) as e:
+        heom.Shard(heom.Hierarchy(workloads.fmo_like(seed=0, depth=5)["system"], 5,
+                                  scaled=True), 2)
+    assert e.value.status == heom.HEOM_E_UNSUPPORTED
