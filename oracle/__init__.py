@@ -71,8 +71,11 @@ def _load():
         lib.oracle_rhs.argtypes = [P(_System), i32, P(d), P(d), i32]
         lib.oracle_propagate.argtypes = [P(_System), i32, P(d), d, i64, i64, P(d), P(d), P(d),
                                          P(d), i32]
+        lib.oracle_rhs_scaled.argtypes = [P(_System), i32, i32, P(d), P(d), i32]
+        lib.oracle_propagate_scaled.argtypes = [P(_System), i32, i32, d, P(d), d, i64, i64, P(d),
+                                                P(d), P(d), P(d), i32]
         for f in (lib.oracle_count, lib.oracle_modes, lib.oracle_enumerate, lib.oracle_rhs,
-                  lib.oracle_propagate):
+                  lib.oracle_propagate, lib.oracle_rhs_scaled, lib.oracle_propagate_scaled):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -145,14 +148,17 @@ def enumerate_ados(sys: dict, depth: int) -> np.ndarray:
     return out
 
 
-def rhs(sys: dict, depth: int, sigma: np.ndarray, scalars=(0.0, 0.0, 0.0), n_threads: int = 1):
-    """Right-hand side for sigma[n_ado, N, N] (oracle order) and (P_trap, P_rec, Q)."""
+def rhs(sys: dict, depth: int, sigma: np.ndarray, scalars=(0.0, 0.0, 0.0), n_threads: int = 1,
+        scaled: bool = False):
+    """Right-hand side for sigma[n_ado, N, N] (oracle order) and (P_trap, P_rec, Q);
+    scaled=True: sigma holds the scaled ADOs and the scaled equations apply."""
     s = System(sys)
     n_ado = sigma.shape[0]
     buf = np.concatenate([np.ascontiguousarray(sigma, np.complex128).view(np.float64).ravel(),
                           np.asarray(scalars, float)])
     out = np.zeros_like(buf)
-    if _load().oracle_rhs(s.ref, depth, _dptr(buf), _dptr(out), n_threads) != 0:
+    if _load().oracle_rhs_scaled(s.ref, depth, int(scaled), _dptr(buf), _dptr(out),
+                                 n_threads) != 0:
         raise ValueError("oracle_rhs failed")
     N = s.N
     f = out[: 2 * n_ado * N * N].view(np.complex128).reshape(n_ado, N, N)
@@ -161,9 +167,11 @@ def rhs(sys: dict, depth: int, sigma: np.ndarray, scalars=(0.0, 0.0, 0.0), n_thr
 
 def propagate(sys: dict, depth: int, rho0: np.ndarray, dt_fs: float, n_steps: int,
               record_every: int = 1, want_state: bool = False, state_in=None,
-              n_threads: int | None = None):
+              n_threads: int | None = None, scaled: bool = False, filter_tol: float = 0.0):
     """Classic RK4 propagation.
 
+    scaled=True propagates the scaled ADOs (the state holds them); filter_tol > 0
+    zeroes, after every step, each ADO n != 0 whose entries are all below it.
     Returns dict(rho=[records, N, N], scalars=[P_trap, P_rec, Q], state=(sigma, scalars)|None).
     """
     s = System(sys)
@@ -183,10 +191,11 @@ def propagate(sys: dict, depth: int, rho0: np.ndarray, dt_fs: float, n_steps: in
                               np.asarray(sc, float)])
     if want_state:
         state = np.zeros(2 * n_ado * N * N + 3)
-    rc = _load().oracle_propagate(s.ref, depth, _dptr(rho0.view(np.float64)), float(dt_fs),
-                                  int(n_steps), int(record_every),
-                                  _dptr(rho_out.view(np.float64)), _dptr(scal), _dptr(state),
-                                  _dptr(sin), int(n_threads))
+    rc = _load().oracle_propagate_scaled(s.ref, depth, int(scaled), float(filter_tol),
+                                         _dptr(rho0.view(np.float64)), float(dt_fs),
+                                         int(n_steps), int(record_every),
+                                         _dptr(rho_out.view(np.float64)), _dptr(scal),
+                                         _dptr(state), _dptr(sin), int(n_threads))
     if rc != 0:
         raise ValueError("oracle_propagate failed")
     res = {"rho": rho_out, "scalars": scal, "state": None}

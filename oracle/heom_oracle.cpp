@@ -22,6 +22,14 @@
 //   * classic fourth-order Runge-Kutta (Appendix B) on the augmented vector
 //     (all sigma_n, P_trap, P_rec, Q) with dQ/dt = P_trap, which gives the mean
 //     trapping time of eq:trappingtime by integration by parts.
+//   * optionally the scaled hierarchy that the introduction names as the way
+//     to fewer auxiliary matrices: every ADO is held divided by
+//     w_n = sqrt(prod_m n_m! |c_m|^n_m) (so sigma_0 is unchanged), which turns
+//     the coupling to n + e_m into sqrt((n_m + 1)|c_m|) i[V, .] and the
+//     coupling to n - e_m into sqrt(n_m / |c_m|) i(c V . - c* . V); and a
+//     filter that, after every RK4 step, sets to zero every ADO n != 0 whose
+//     stored entries are all below a threshold in absolute value (real and
+//     imaginary parts).
 //
 // Readings of points the paper leaves open (each is also listed in the design
 // notes of the repository):
@@ -77,6 +85,8 @@ struct Mode {
 struct Model {
   int N = 0;
   int depth = 0;
+  bool scaled = false;      // ADOs held divided by w_n (see the header)
+  double filter_tol = 0.0;  // > 0: filter after every step
   Mat H;                          // rad/fs, as given
   std::vector<double> trap, rec;  // 1/fs, per site
   std::vector<double> delta;      // low-temperature-correction residual per site
@@ -282,19 +292,22 @@ Mat rhs_one(const Model& m, const Mat& Heff, const Mat& HeffDag, const State& x,
   }
   for (int mode = 0; mode < M; ++mode) {
     const int s = m.modes[mode].site;
-    // Coupling to the deeper ADO: + i [V_s, sigma_{n+e_m}].
+    // Coupling to the deeper ADO: + i [V_s, sigma_{n+e_m}] (scaled form:
+    // w_{n+e_m} / w_n = sqrt((n_m + 1)|c_m|) times it).
+    const cplx c = m.modes[mode].c;
     const int u = m.up[n][mode];
     if (u >= 0) {
       const Mat& Y = x.sigma[u];
       Mat L = proj_left(s, Y, N), R = proj_right(s, Y, N);
-      for (int k = 0; k < N * N; ++k) out[k] += I * (L[k] - R[k]);
+      const double wu = m.scaled ? std::sqrt((m.ados[n][mode] + 1.0) * std::abs(c)) : 1.0;
+      for (int k = 0; k < N * N; ++k) out[k] += wu * (I * (L[k] - R[k]));
     }
-    // Coupling to the shallower ADO: + n_m i (c V_s Z - c* Z V_s).
+    // Coupling to the shallower ADO: + n_m i (c V_s Z - c* Z V_s) (scaled
+    // form: n_m w_{n-e_m} / w_n = sqrt(n_m / |c_m|) in place of n_m).
     const int d = m.down[n][mode];
     if (d >= 0) {
       const Mat& Z = x.sigma[d];
-      const double nm = m.ados[n][mode];
-      const cplx c = m.modes[mode].c;
+      const double nm = m.scaled ? std::sqrt(m.ados[n][mode] / std::abs(c)) : m.ados[n][mode];
       Mat L = proj_left(s, Z, N), R = proj_right(s, Z, N);
       for (int k = 0; k < N * N; ++k) out[k] += nm * I * (c * L[k] - std::conj(c) * R[k]);
     }
@@ -350,6 +363,17 @@ void rk4_step(const Model& m, State* y, double dt, int n_threads) {
   y->p_trap += (dt / 6.0) * (k1.p_trap + 2.0 * k2.p_trap + 2.0 * k3.p_trap + k4.p_trap);
   y->p_rec += (dt / 6.0) * (k1.p_rec + 2.0 * k2.p_rec + 2.0 * k3.p_rec + k4.p_rec);
   y->q += (dt / 6.0) * (k1.q + 2.0 * k2.q + 2.0 * k3.q + k4.q);
+}
+
+// The filter: every ADO n != 0 whose entries (real and imaginary parts) are
+// all below tol in absolute value becomes zero.
+void filter_state(State* y, double tol) {
+  for (size_t n = 1; n < y->sigma.size(); ++n) {
+    double mx = 0.0;
+    for (const cplx& v : y->sigma[n]) mx = std::fmax(mx, std::fmax(std::fabs(v.real()), std::fabs(v.imag())));
+    if (mx < tol)
+      for (cplx& v : y->sigma[n]) v = cplx(0.0, 0.0);
+  }
 }
 
 void load_state(const Model& m, const double* in, State* x) {
@@ -422,6 +446,19 @@ int oracle_enumerate(const oracle_system* s, int32_t depth, int32_t* out) {
 // Right-hand side for an arbitrary state (not necessarily Hermitian).
 // State layout: n_ado blocks of N*N complex (interleaved re, im), row-major,
 // in the oracle's order, followed by 3 doubles (P_trap, P_rec, Q).
+// scaled = 1: the state holds the scaled ADOs and the scaled equations apply.
+int oracle_rhs_scaled(const oracle_system* s, int32_t depth, int32_t scaled,
+                      const double* state_in, double* state_out, int32_t n_threads) {
+  Model m;
+  if (!build_model(s, depth, &m)) return -1;
+  m.scaled = scaled != 0;
+  State x, f;
+  load_state(m, state_in, &x);
+  rhs(m, x, &f, n_threads);
+  store_state(m, f, state_out);
+  return 0;
+}
+
 int oracle_rhs(const oracle_system* s, int32_t depth, const double* state_in, double* state_out,
                int32_t n_threads) {
   Model m;
@@ -438,12 +475,17 @@ int oracle_rhs(const oracle_system* s, int32_t depth, const double* state_in, do
 //   scalars_out  [3] = P_trap, P_rec, Q at the end, or NULL
 //   state_out    full final state as in oracle_rhs, or NULL
 //   state_in     full initial state as in oracle_rhs (overrides rho0), or NULL
-int oracle_propagate(const oracle_system* s, int32_t depth, const double* rho0, double dt_fs,
-                     int64_t n_steps, int64_t record_every, double* rho_out, double* scalars_out,
-                     double* state_out, const double* state_in, int32_t n_threads) {
+//   scaled       1: propagate the scaled ADOs (state_in / state_out hold them)
+//   filter_tol   > 0: filter the state after every step
+int oracle_propagate_scaled(const oracle_system* s, int32_t depth, int32_t scaled,
+                            double filter_tol, const double* rho0, double dt_fs, int64_t n_steps,
+                            int64_t record_every, double* rho_out, double* scalars_out,
+                            double* state_out, const double* state_in, int32_t n_threads) {
   Model m;
   if (!build_model(s, depth, &m)) return -1;
-  if (dt_fs <= 0.0 || n_steps < 0 || record_every < 1) return -1;
+  if (dt_fs <= 0.0 || n_steps < 0 || record_every < 1 || !(filter_tol >= 0.0)) return -1;
+  m.scaled = scaled != 0;
+  m.filter_tol = filter_tol;
   const int N2 = m.N * m.N;
   State y;
   if (state_in) {
@@ -462,6 +504,7 @@ int oracle_propagate(const oracle_system* s, int32_t depth, const double* rho0, 
   }
   for (int64_t step = 1; step <= n_steps; ++step) {
     rk4_step(m, &y, dt_fs, n_threads);
+    if (m.filter_tol > 0.0) filter_state(&y, m.filter_tol);
     if (rho_out && step % record_every == 0) {
       double* o = rho_out + 2 * rec * N2;
       for (int k = 0; k < N2; ++k) {
@@ -478,6 +521,13 @@ int oracle_propagate(const oracle_system* s, int32_t depth, const double* rho0, 
   }
   if (state_out) store_state(m, y, state_out);
   return 0;
+}
+
+int oracle_propagate(const oracle_system* s, int32_t depth, const double* rho0, double dt_fs,
+                     int64_t n_steps, int64_t record_every, double* rho_out, double* scalars_out,
+                     double* state_out, const double* state_in, int32_t n_threads) {
+  return oracle_propagate_scaled(s, depth, 0, 0.0, rho0, dt_fs, n_steps, record_every, rho_out,
+                                 scalars_out, state_out, state_in, n_threads);
 }
 
 }  // extern "C"

@@ -16,7 +16,13 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTATIONS = {
-    "up_coupling_sign": ("out[k] += I * (L[k] - R[k]);", "out[k] -= I * (L[k] - R[k]);"),
+    "up_coupling_sign": ("out[k] += wu * (I * (L[k] - R[k]));",
+                         "out[k] -= wu * (I * (L[k] - R[k]));"),
+    "scaled_up_weight": ("std::sqrt((m.ados[n][mode] + 1.0) * std::abs(c))",
+                         "std::sqrt((m.ados[n][mode] + 0.0) * std::abs(c))"),
+    "scaled_down_weight": ("std::sqrt(m.ados[n][mode] / std::abs(c))",
+                           "std::sqrt(m.ados[n][mode] * std::abs(c))"),
+    "filter_inverted": ("if (mx < tol)", "if (mx > tol)"),
     "dropped_damping": ("axpy(&out, cplx(-damp, 0.0), X);", "(void)damp;"),
     "down_missing_conj": ("std::conj(c) * R[k]", "c * R[k]"),
     "down_missing_occupation": ("out[k] += nm * I *", "out[k] += I *"),
