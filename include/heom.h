@@ -44,7 +44,9 @@ enum {
   HEOM_E_INVALID = -1,     /* an argument failed validation                     */
   HEOM_E_NOMEM = -2,       /* host or device allocation failed                  */
   HEOM_E_DEVICE = -3,      /* a HIP runtime call failed (text in last error)    */
-  HEOM_E_NUMERIC = -4,     /* NaN/Inf in the reduced density matrix             */
+  HEOM_E_NUMERIC = -4,     /* NaN/Inf in the reduced density matrix, or a drift
+                              of Tr rho + P_trap + P_rec (conserved exactly)
+                              beyond 1e-7 relative (HEOM_DRIFT_TOL overrides) */
   HEOM_E_WORKSPACE = -5,   /* workspace missing, too small or misaligned        */
   HEOM_E_UNSUPPORTED = -6  /* valid request this build cannot serve             */
 };
@@ -174,7 +176,9 @@ int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, d
  *   sinks_out      host [3] = {P_trap, P_recomb, Q = int_0^t P_trap dt'} after
  *                  the last step, or NULL
  * Errors: HEOM_E_INVALID, HEOM_E_WORKSPACE, HEOM_E_DEVICE, HEOM_E_NUMERIC
- * (NaN/Inf in a recorded rho; the run stops there). */
+ * (NaN/Inf in a recorded rho, or Tr rho + P_trap + P_rec moved from its value
+ * at the call's first record by more than 1e-7 relative, or the value of the
+ * environment variable HEOM_DRIFT_TOL; the run stops there). */
 int heom_propagate(heom_hierarchy *h, int precision, int flags, const double *rho0, double dt_fs,
                    int64_t n_steps, int64_t record_every, void *d_workspace,
                    size_t workspace_bytes, void *hip_stream, double *rho_out, double *sinks_out);

@@ -229,6 +229,17 @@ void unpack_hermitian(int N, const double *packed, double *rho) {
 // Steps captured in one graph.
 constexpr int64_t kGraphSteps = 32;
 
+// Tolerance of the population health check (relative to the conserved
+// value); HEOM_DRIFT_TOL overrides it.
+double population_drift_tol() {
+  const char *s = std::getenv("HEOM_DRIFT_TOL");
+  if (s && s[0]) {
+    const double v = std::atof(s);
+    if (v > 0.0) return v;
+  }
+  return 1e-7;
+}
+
 // MI355X has 8 XCDs, each with its own L2; workgroups are dispatched to them
 // round-robin by workgroup index.
 constexpr int64_t kXcds = 8;
@@ -642,6 +653,14 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   bool want_rho = false;
   for (int k = 0; rho_outs && k < n; ++k) want_rho = want_rho || rho_outs[k] != nullptr;
   std::vector<std::vector<double>> host_ring(n);
+  // Health check of every record: Tr sigma_0 + P_trap + P_rec is conserved
+  // exactly by the equations and by RK4 (every term but the sinks is
+  // traceless, and the sinks feed P_trap and P_rec), in both precisions (the
+  // diagonal of sigma_0 and the scalars are FP64).  Its value at the first
+  // record of the call is the reference; a drift beyond the tolerance means a
+  // corrupted state.
+  const double drift_tol = population_drift_tol();
+  std::vector<double> pop_ref(n, std::nan(""));
   int slot = 0;
   int64_t rec_done = 0;
   auto drain = [&]() -> int {
@@ -665,6 +684,17 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
           if (!std::isfinite(src[q]))
             return fail(HEOM_E_NUMERIC, "non-finite reduced density matrix at record " +
                                             std::to_string(rec_done + s));
+        if (check_numeric) {
+          double pop = src[N * N] + src[N * N + 1];  // P_trap + P_rec
+          for (int a = 0; a < N; ++a) pop += src[a];
+          if (std::isnan(pop_ref[k])) pop_ref[k] = pop;
+          if (std::fabs(pop - pop_ref[k]) > drift_tol * std::fmax(1.0, std::fabs(pop_ref[k])))
+            return fail(HEOM_E_NUMERIC,
+                        "population drift at record " + std::to_string(rec_done + s) +
+                            ": Tr rho + P_trap + P_rec moved by " +
+                            std::to_string(pop - pop_ref[k]) + " (instance " +
+                            std::to_string(k) + ")");
+        }
         unpack_hermitian(N, src, rho_outs[k] + 2 * static_cast<size_t>(N) * N * (rec_done + s));
       }
     }

@@ -406,3 +406,23 @@ def test_served_results_equal_alone_and_oracle():
         ref = oracle.propagate(r.system, r.depth, r.rho0, 1.0, r.steps, record_every=r.steps)
         assert _rel(r.rho_final, ref["rho"][-1]) <= FP64_TOL
         assert abs(r.sinks[0] - ref["scalars"][0]) <= FP64_TOL * max(ref["scalars"][0], 1e-300)
+
+
+def test_population_drift_health_check(monkeypatch):
+    """Tr rho + P_trap + P_rec is conserved exactly by the equations and by
+    RK4; the library checks every record against the call's first and stops
+    with HEOM_E_NUMERIC beyond 1e-7 relative (HEOM_DRIFT_TOL).  The failure
+    is forced from the host with a tolerance below rounding; every kernel
+    still runs normally."""
+    w = workloads.fmo_like(seed=0, site=1, depth=3, steps=200)
+    _say("case: population health check (default passes, tolerance 1e-300 trips)")
+    h = heom.Hierarchy(w["system"], 3)
+    rho, sinks, _ = heom.propagate(h, w["rho0"], 1.0, 200, record_every=1)
+    assert sinks[0] > 0.01  # population really moved to the sinks
+    monkeypatch.setenv("HEOM_DRIFT_TOL", "1e-300")
+    with pytest.raises(heom.HeomError) as e:
+        heom.propagate(h, w["rho0"], 1.0, 200, record_every=1)
+    assert e.value.status == heom.HEOM_E_NUMERIC and "population drift" in str(e.value)
+    monkeypatch.delenv("HEOM_DRIFT_TOL")
+    rho2, sinks2, _ = heom.propagate(h, w["rho0"], 1.0, 200, record_every=1)
+    assert np.array_equal(rho2, rho) and np.array_equal(sinks2, sinks)
