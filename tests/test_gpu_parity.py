@@ -418,7 +418,7 @@ def test_population_drift_health_check(monkeypatch):
     _say("case: population health check (default passes, tolerance 1e-300 trips)")
     h = heom.Hierarchy(w["system"], 3)
     rho, sinks, _ = heom.propagate(h, w["rho0"], 1.0, 200, record_every=1)
-    assert sinks[0] > 0.01  # population really moved to the sinks
+    assert sinks[0] > 1e-3  # population really moved to the sinks
     monkeypatch.setenv("HEOM_DRIFT_TOL", "1e-300")
     with pytest.raises(heom.HeomError) as e:
         heom.propagate(h, w["rho0"], 1.0, 200, record_every=1)
