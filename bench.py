@@ -45,10 +45,9 @@ ALG_ADOS_PER_LAUNCH = 4.0
 MOVED_ADOS_PER_LAUNCH = 11.0 / 4.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(ROOT, "tests", "golden")
-# rocprofv3 summaries of the dominant kernels (FETCH_SIZE / WRITE_SIZE
-# traffic), and the sources whose digest they record.
-PROFILES = {"sweep": os.path.join(ROOT, "profiles", "stage_tile_7_k1_fp64_sweep64.md"),
-            "fmo": os.path.join(ROOT, "profiles", "stage_tile_7_fp64_fmo_batch.md")}
+# rocprofv3 summaries of the stage kernels (FETCH_SIZE / WRITE_SIZE traffic
+# per launch, by kernel and workload) and the sources whose digest they record.
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1012_4382_amd/csrc/stage_kernels.h",
                   "paper_1012_4382_amd/csrc/heom_internal.h",
                   "paper_1012_4382_amd/csrc/kernels_tile_7.hip", "paper_1012_4382_amd/build.py"]
@@ -73,19 +72,27 @@ def _kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def _profiled_traffic(which: str, kernel: str):
-    """Counted HBM bytes per launch from the committed profile, or None when
-    the profile is of another kernel or of sources that have changed since."""
+def _profiled_traffic(workload: str, kernel: str):
+    """Counted HBM bytes per launch of `kernel` on `workload` from the committed
+    profiles (a block of "- kernel:", "- workload:", "- source digest:" and
+    "- traffic per launch (bytes):" lines), or None when no profile covers it
+    or its sources have changed since."""
+    digest = _kernel_digest()
     try:
-        text = open(PROFILES[which]).read()
+        names = sorted(f for f in os.listdir(PROFILE_DIR) if f.endswith(".md"))
     except OSError:
         return None
-    k = re.search(r"^- kernel: `([^`]+)`", text, re.M)
-    d = re.search(r"^- source digest: `([0-9a-f]+)`", text, re.M)
-    t = re.search(r"^- traffic per launch \(bytes\): (\d+)", text, re.M)
-    if not (k and d and t) or k.group(1) != kernel or d.group(1) != _kernel_digest():
-        return None
-    return float(t.group(1))
+    for name in names:
+        text = open(os.path.join(PROFILE_DIR, name)).read()
+        for block in re.split(r"(?m)^(?=- kernel: )", text)[1:]:
+            k = re.search(r"^- kernel: `([^`]+)`", block, re.M)
+            w = re.search(r"^- workload: `([^`]+)`", block, re.M)
+            d = re.search(r"^- source digest: `([0-9a-f]+)`", block, re.M)
+            t = re.search(r"^- traffic per launch \(bytes\): (\d+)", block, re.M)
+            if (k and w and d and t and k.group(1) == kernel and w.group(1) == workload and
+                    d.group(1) == digest):
+                return float(t.group(1))
+    return None
 
 
 def _parse():
@@ -100,12 +107,19 @@ def _parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fmo", action="store_true",
                    help="skip the FMO-shaped 8-solve batch (depth 7, 5 ps)")
+    p.add_argument("--fmo-steps", type=int, default=5000,
+                   help="RK4 steps of the FMO-shaped batch (5000: 5 ps, checked against the "
+                        "oracle; fewer for profiler runs, then unchecked)")
     p.add_argument("--no-variants", action="store_true",
                    help="skip single-solve, FP32-mixed and one-at-a-time rates and precision")
     p.add_argument("--kernel", default="auto", choices=["auto", "lane", "generic"],
                    help="stage kernel (lane and generic are diagnostic)")
     p.add_argument("--no-sizing", action="store_true",
                    help="skip the depth-16 and 24-site sizing launches")
+    p.add_argument("--no-shard", action="store_true",
+                   help="skip the depth-16 hierarchy split over 8 ranks")
+    p.add_argument("--no-scaled", action="store_true",
+                   help="skip the scaled hierarchy and its filter at depths 12 and 16")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 256 MiB device copy (reference for traffic counters)")
     p.add_argument("--no-batch-scaling", action="store_true",
@@ -145,11 +159,11 @@ def _timed(run, stream, torch, reps, warmup, launches_per_rep):
     return el, ev0.elapsed_time(ev1) / (reps * launches_per_rep), out
 
 
-def _roofline(which, kernel, n_ados, N, s, k_ms):
+def _roofline(workload, kernel, n_ados, N, s, k_ms):
     """Roofline object of a stage launch over n_ados ADOs that took k_ms."""
     alg = n_ados * ALG_ADOS_PER_LAUNCH * N * N * s
     moved = n_ados * MOVED_ADOS_PER_LAUNCH * N * N * s
-    traffic = _profiled_traffic(which, kernel)
+    traffic = _profiled_traffic(workload, kernel)
     r = {"bound": "hbm", "achieved": alg / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
          "unit": "GB/s", "frac": alg / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
          "kernel": kernel, "kernel_avg_us": k_ms * 1e3, "bytes_per_launch": alg,
@@ -165,7 +179,10 @@ def _roofline(which, kernel, n_ados, N, s, k_ms):
 def _kernel_name(heom, N, KP, n_tiles, precision, kernel):
     shape, shape_us, streaming, streaming_us = heom.autotune_lookup(N, KP, n_tiles, precision)
     T = "double" if precision == "fp64" else "float"
-    name = {"auto": (f"stage_tile<{N},{KP},{T},{max(shape, 0)}>" if shape != 5
+    # The 64-ADO tile kernel is built up to 12 sites; above that the wide
+    # kernel is the only LDS-tiled choice and is not tuned.
+    wide = shape == 5 or N > 12
+    name = {"auto": (f"stage_tile<{N},{KP},{T},{max(shape, 0)}>" if not wide
                      else f"stage_wide<{T},{KP}>")
                     + (" with streaming stores" if streaming == 1 else ""),
             "lane": f"stage_fixed<{N},{KP},{T}>",
@@ -181,8 +198,8 @@ def _kernel_name(heom, N, KP, n_tiles, precision, kernel):
 def _check_sweep(rhos, sinks, golden, prec):
     """The timed sweep's instances against the oracle's stored trajectories:
     max relative deviation of sigma_0 (every 100 steps) and of P_trap."""
-    if golden is None:
-        return None
+    if golden is None or len(rhos[0]) != len(golden["rho"][0]):
+        return None  # no stored trajectory, or a run of another length
     idx = [int(i) for i in golden["instances"]]
     drho = max(float(np.max(np.abs(rhos[i] - golden["rho"][k])) / np.max(np.abs(golden["rho"][k])))
                for k, i in enumerate(idx))
@@ -198,7 +215,8 @@ def _fmo_batch(heom, torch, workloads, stream, args):
     every 10 steps, FP64: timed like the headline, its roofline, and its
     timed runs against the oracle's trajectories (populations every 10 steps,
     sigma_0 every 100, eta at 5 ps)."""
-    batch = workloads.fmo_like_batch(steps=5000)
+    steps = args.fmo_steps
+    batch = workloads.fmo_like_batch(steps=steps)
     hs = [heom.Hierarchy(w["system"], w["depth"]) for w in batch]
     r0 = [w["rho0"] for w in batch]
     N = hs[0].N
@@ -206,19 +224,20 @@ def _fmo_batch(heom, torch, workloads, stream, args):
     ws = heom.allocate_workspace(heom.batch_workspace_bytes(hs, "fp64"))
 
     def run():
-        return heom.propagate_batch(hs, r0, 1.0, 5000, record_every=10, workspace=ws,
+        return heom.propagate_batch(hs, r0, 1.0, steps, record_every=10, workspace=ws,
                                     stream=stream, kernel=args.kernel)
 
     reps = max(2, args.steps // 4)
-    el, k_ms, (rhos, sinks, _) = _timed(run, stream, torch, reps, 1, 4 * 5000)
+    el, k_ms, (rhos, sinks, _) = _timed(run, stream, torch, reps, 1, 4 * steps)
     name, tune = _kernel_name(heom, N, 1, sum((h.n_ados + 63) // 64 for h in hs), "fp64",
                               args.kernel)
-    out = {"workload": "fmo_like_7site_depth7_fp64_8solves_5ps", "n_ados": total,
-           "passes": reps, "ado_steps_per_s": total * 5000 * reps / el,
-           "ms_per_pass": 1e3 * el / reps, "roofline": _roofline("fmo", name, total, N, 8, k_ms),
+    out = {"workload": f"fmo_like_7site_depth7_fp64_8solves_{steps}steps", "n_ados": total,
+           "passes": reps, "ado_steps_per_s": total * steps * reps / el,
+           "ms_per_pass": 1e3 * el / reps,
+           "roofline": _roofline("fmo_like_7site_depth7_fp64_8solves", name, total, N, 8, k_ms),
            "autotune": tune}
     g = _load_golden("oracle_fmo_like_depth7.npz")
-    if g is not None:
+    if g is not None and steps == int(g["steps"]):
         pops = [np.real(np.diagonal(r, axis1=1, axis2=2)) for r in rhos]
         out["check_vs_oracle"] = {
             "solves": len(hs),
@@ -398,11 +417,19 @@ def _sizing(heom, torch, workloads, stream, kernel):
     w = workloads.fmo_like(seed=0, site=1, depth=16, steps=200)
     h = heom.Hierarchy(w["system"], w["depth"])
     out = {"workload": "fmo_like_7site_depth16_single_solve", "n_ados": h.n_ados}
+    return _sizing_rows(heom, torch, h, w, stream, kernel, out)
+
+
+def _sizing_rows(heom, torch, h, w, stream, kernel, out):
+    """FP64 and FP32-mixed rows of a one-solve sizing leg: ADO-steps/s and the
+    stage kernel's roofline (counted traffic from the committed profiles)."""
     for prec, s in (("fp64", 8), ("fp32", 4)):
         k_ms, rate = _stage_kernel_timing(heom, torch, [h], [w["rho0"]], stream, kernel, prec,
                                           steps=100)
-        out[prec] = {"ado_steps_per_s": rate, "kernel_avg_us": k_ms * 1e3,
-                     **_rates(h.n_ados, h.N, s, k_ms)}
+        name, _ = _kernel_name(heom, h.N, h.n_modes // h.N, (h.n_ados + 63) // 64, prec, kernel)
+        out[prec] = {"ado_steps_per_s": rate,
+                     "roofline": _roofline(f"{out['workload']}_{prec}", name, h.n_ados, h.N, s,
+                                           k_ms)}
     return out
 
 
@@ -415,12 +442,7 @@ def _wide_sizing(heom, torch, workloads, stream, kernel):
     h = heom.Hierarchy(w["system"], w["depth"])
     out = {"workload": f"serving_24site_{w['topology']}_depth4_single_solve",
            "n_ados": h.n_ados}
-    for prec, s in (("fp64", 8), ("fp32", 4)):
-        k_ms, rate = _stage_kernel_timing(heom, torch, [h], [w["rho0"]], stream, kernel, prec,
-                                          steps=100)
-        out[prec] = {"ado_steps_per_s": rate, "kernel_avg_us": k_ms * 1e3,
-                     **_rates(h.n_ados, h.N, s, k_ms)}
-    return out
+    return _sizing_rows(heom, torch, h, w, stream, kernel, out)
 
 
 def _shard_sizing(heom, torch, workloads, stream, ranks=8, steps=100):
@@ -484,13 +506,28 @@ def _scaled_filtered(heom, torch, workloads, stream, depths=(12, 16), tols=(1e-6
             sig, _ = heom.read_state(h, ws, stream=stream)
             nz = np.max(np.abs(sig), axis=(1, 2)) > 0
             kept = int(np.sum(nz))
-            tiers = np.sum(h.tables()[0], axis=1)
+            multi, up, down = h.tables()
+            tiers = np.sum(multi, axis=1)
             by_tier = [int(np.sum(nz[tiers == t])) for t in range(D + 1)]
+            # 64-ADO tiles (in the library's order) that hold a nonzero ADO, and
+            # those within 4 links of one: one RK4 step reaches 4 links, so only
+            # those tiles can change in the next step.
+            reach = nz.copy()
+            for _ in range(4):
+                nxt = reach.copy()
+                for tab in (up, down):
+                    src = np.nonzero(reach[:, None] & (tab >= 0))
+                    nxt[tab[src]] = True
+                reach = nxt
+            tiles_nz = int(np.unique(np.nonzero(nz)[0] // 64).size)
+            tiles_reach = int(np.unique(np.nonzero(reach)[0] // 64).size)
             del sig, ws
             entry = {"filter_tol": tol, "eta": float(sk[0]),
                      "abs_eta_error_vs_plain": abs(float(sk[0]) - float(s0[0])),
                      "ados_nonzero_at_end": kept, "kept_fraction": kept / h.n_ados,
-                     "nonzero_by_tier": by_tier, "seconds": el}
+                     "nonzero_by_tier": by_tier, "tiles": (h.n_ados + 63) // 64,
+                     "tiles_nonzero": tiles_nz, "tiles_within_4_links": tiles_reach,
+                     "seconds": el}
             row["filtered"].append(entry)
             h.close()
         out["rows"].append(row)
@@ -626,7 +663,8 @@ def main():
     n_tiles = sum((h.n_ados + 63) // 64 for h in hs)
     kernel_name, autotune = _kernel_name(heom, N, KP, n_tiles, prec, args.kernel)
     s_bytes = 8 if prec == "fp64" else 4
-    roof = _roofline("sweep", kernel_name, total_ados, N, s_bytes, kernel_ms)
+    roof = _roofline(f"sweep_64x_fmo_like_7site_k1_depth3to5_{prec}", kernel_name, total_ados, N,
+                     s_bytes, kernel_ms)
     roof["kernel_avg_us_note"] = ("device time of the timed passes per stage launch (HIP events "
                                   "on the library's stream), an upper bound of the kernel's "
                                   "average duration: it includes the gaps between launches "
@@ -682,7 +720,9 @@ def main():
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
         result["wide_sizing"] = _wide_sizing(heom, torch, workloads, stream, args.kernel)
+    if not args.no_shard:
         result["shard_sizing"] = _shard_sizing(heom, torch, workloads, stream)
+    if not args.no_scaled:
         result["scaled_filtered"] = _scaled_filtered(heom, torch, workloads, stream)
     if not args.no_batch_scaling:
         result["batch_scaling"] = _batch_scaling(heom, torch, workloads, stream, args.kernel)
