@@ -546,8 +546,10 @@ def _batch_scaling(heom, torch, workloads, stream, kernel, sizes=(2, 4, 8, 16, 3
         r0 = [w["rho0"] for w in batch]
         row = {"solves": n, "n_ados": sum(h.n_ados for h in hs)}
         for prec, s in (("fp64", 8), ("fp32", 4)):
+            # 500 steps, so that the capture of the run's graphs (once per call)
+            # weighs little on the small launches.
             k_ms, rate = _stage_kernel_timing(heom, torch, hs, r0, stream, kernel, prec,
-                                              steps=100)
+                                              steps=500)
             row[prec] = {"ado_steps_per_s": rate, "kernel_avg_us": k_ms * 1e3,
                          **_rates(row["n_ados"], hs[0].N, s, k_ms)}
         rows.append(row)
