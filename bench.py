@@ -114,6 +114,8 @@ def _parse():
                    help="skip single-solve, FP32-mixed and one-at-a-time rates and precision")
     p.add_argument("--kernel", default="auto", choices=["auto", "lane", "generic"],
                    help="stage kernel (lane and generic are diagnostic)")
+    p.add_argument("--no-small", action="store_true",
+                   help="skip the small-hierarchy runs (resident kernel against stage launches)")
     p.add_argument("--no-sizing", action="store_true",
                    help="skip the depth-16 and 24-site sizing launches")
     p.add_argument("--no-shard", action="store_true",
@@ -409,6 +411,49 @@ def _stage_kernel_timing(heom, torch, hs, rho0s, stream, kernel, precision="fp64
         total_ms = min(total_ms, ev0.elapsed_time(ev1))
     ados = sum(h.n_ados for h in hs)
     return total_ms / (4 * steps), ados * steps / (total_ms * 1e-3)
+
+
+def _small(heom, torch, workloads, stream, reps=5):
+    """Small hierarchies, where a stage launch lasts about its launch floor:
+    the dimer (15 ADOs, 1000 steps, every step recorded), a 3-site solve with a
+    Matsubara term (84 ADOs) and a 7-site depth-2 solve (36 ADOs; outside the
+    resident kernel's domain, so both columns are stage launches), 5000 steps
+    with records every 10, each on the default path (the resident kernel where
+    the run fits it: every step of a chunk in one launch) and on the
+    stage-per-launch path, wall clock per solve (the faster of `reps`),
+    results compared bitwise."""
+    rng = np.random.default_rng(5)
+    tr, rc = workloads.fmo_sinks(N=3, trap_site=2)
+    three = {"system": workloads.system(workloads.fmo_like_hamiltonian(rng, N=3), lam=60.0,
+                                        gamma_inv_fs=80.0, T=150.0, K=1, trap=tr, rec=rc),
+             "depth": 3, "rho0": workloads.site_state(3, 1)}
+    cases = [("dimer_depth4_1000steps_every_step", workloads.dimer(), 1000, 1),
+             ("3site_k1_depth3_5000steps", three, 5000, 10),
+             ("fmo_like_7site_depth2_5000steps", workloads.fmo_like(seed=0, site=1, depth=2),
+              5000, 10)]
+    out = {}
+    for name, w, steps, rec in cases:
+        h = heom.Hierarchy(w["system"], w["depth"])
+        ws = heom.allocate_workspace(h.workspace_bytes[heom.HEOM_FP64])
+        row, res = {"n_ados": h.n_ados, "rk4_steps": steps}, {}
+        for kernel in ("auto", "tiled"):
+            best = float("inf")
+            for _ in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res[kernel] = heom.propagate(h, w["rho0"], 1.0, steps, record_every=rec,
+                                             workspace=ws, stream=stream, kernel=kernel)[:2]
+                best = min(best, time.perf_counter() - t0)
+            key = "resident" if kernel == "auto" else "stage_launches"
+            row[key] = {"ms_per_solve": best * 1e3, "ado_steps_per_s": h.n_ados * steps / best,
+                        "us_per_step": best * 1e6 / steps}
+        row["resident_over_stage_launches"] = (row["stage_launches"]["ms_per_solve"] /
+                                               row["resident"]["ms_per_solve"])
+        row["bitwise_equal"] = bool(np.array_equal(res["auto"][0], res["tiled"][0]) and
+                                    np.array_equal(res["auto"][1], res["tiled"][1]))
+        out[name] = row
+        h.close()
+    return out
 
 
 def _sizing(heom, torch, workloads, stream, kernel):
@@ -719,6 +764,8 @@ def main():
             f"{prec}_batched_over_one_at_a_time": value / (total_ados * steps_rk / el_1)}
     if not args.no_fmo:
         result["fmo_batch"] = _fmo_batch(heom, torch, workloads, stream, args)
+    if not args.no_small:
+        result["small_hierarchies"] = _small(heom, torch, workloads, stream)
     if not args.no_sizing:
         result["hbm_sizing"] = _sizing(heom, torch, workloads, stream, args.kernel)
         result["wide_sizing"] = _wide_sizing(heom, torch, workloads, stream, args.kernel)

@@ -70,10 +70,17 @@ enum {
   HEOM_STREAMING_STORES = 32, /* FP64 tile kernels write their output with
                                non-temporal (streaming) stores (other kernels
                                always store plainly)                            */
-  HEOM_PLAIN_STORES = 64    /* tile kernels write their output with plain
+  HEOM_PLAIN_STORES = 64,   /* tile kernels write their output with plain
                                stores (exclusive with HEOM_STREAMING_STORES;
                                without either, the autotuner's policy, or
                                plain stores where no tuning is done)            */
+  HEOM_NO_RESIDENT = 128    /* diagnostic: launch every RK4 stage even where
+                               the run fits the resident kernel (FP64, real H,
+                               unscaled, N <= 4 and at most 1024 packed
+                               elements x ADOs per instance: all steps of a
+                               chunk in one launch, one workgroup per instance,
+                               the hierarchy in LDS; results are bitwise the
+                               same)                                          */
 };
 /* Flag bits that force tile launch shape s (0 <= s < heom_tile_shape_count())
  * for every tile-kernel group of a call. */

@@ -5,6 +5,7 @@
 #include <mutex>
 
 #include "stage_kernels.h"
+#include "resident_kernel.h"
 
 namespace heom {
 
@@ -151,6 +152,28 @@ hipError_t prepare_wide(int N, int M, bool mixed, int levels) {
   const void *k = wide_kernel(mixed, M / N, levels > 0);
   if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// LDS bytes the resident kernel needs for an instance of n ADOs.
+int resident_lds_bytes(int N, int M, int64_t n_ados) {
+  return resident_lds(N, M, static_cast<int>(n_ados)).total;
+}
+
+// Lets the resident kernel take `bytes` of dynamic LDS.
+hipError_t prepare_resident(int bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_resident),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// Steps step0 + 1 ... step0 + n_steps of n_inst resident instances, one
+// workgroup each (descs[0 .. n_inst - 1]).
+hipError_t launch_resident(const InstDesc *descs, int n_inst, int64_t step0, int64_t n_steps,
+                           int64_t record_every, int slot0, double dt, int lds_bytes,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(stage_resident, dim3(n_inst), dim3(kResidentThreads),
+                     static_cast<size_t>(lds_bytes), stream, descs, step0, n_steps, record_every,
+                     slot0, dt);
+  return hipGetLastError();
 }
 
 // `streaming` selects the tile kernel instance with non-temporal output

@@ -37,6 +37,11 @@ hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, 
 hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
                            hipStream_t stream);
 hipError_t static_scratch(int device, void **ptr);
+int resident_lds_bytes(int N, int M, int64_t n_ados);
+hipError_t prepare_resident(int bytes);
+hipError_t launch_resident(const InstDesc *descs, int n_inst, int64_t step0, int64_t n_steps,
+                           int64_t record_every, int slot0, double dt, int lds_bytes,
+                           hipStream_t stream);
 hipError_t launch_halo(bool mixed, const InstDesc *descs, const HaloEntry *list, int n,
                        int stage, hipStream_t stream);
 
@@ -390,6 +395,40 @@ int forced_streaming(int flags) {
 
 constexpr int kShapeFlagMask = 0xf00;
 
+// LDS of one CU that the resident kernel may take, and its longest launch in
+// steps (a launch of a long run is cut into chunks of this many steps).
+constexpr int kResidentMaxLds = 160 * 1024;
+constexpr int64_t kResidentChunkSteps = 4096;
+// Where one workgroup runs a stage faster than a stage launch: at most one
+// packed element of one ADO per thread, and few sites (the resident kernel
+// takes N at run time, so its per-element chain grows with N; measured: the
+// dimer 2.3x faster, 7 sites at depth 2 0.86x).
+constexpr int64_t kResidentMaxItems = 1024;
+constexpr int kResidentMaxSites = 4;
+
+// LDS bytes of the resident kernel for the instances of a call, or 0 when the
+// call does not fit it: FP64 storage, hierarchies the LDS-tiled kernels run
+// (real H), unscaled and unfiltered, no split, small enough, and no flag that
+// asks for another kernel.
+int resident_bytes(heom_hierarchy *const *hs, int n, bool mixed, int flags, bool split) {
+  if (mixed || split || n < 1) return 0;
+  if (flags & (HEOM_NO_RESIDENT | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)) return 0;
+  if (forced_shape(flags) >= 0) return 0;
+  int bytes = 0;
+  for (int k = 0; k < n; ++k) {
+    const heom_hierarchy *h = hs[k];
+    // The LDS-tiled kernels' domain (real H, N and K+1 they are built for):
+    // there the two paths agree bitwise.
+    if (!h->h_real || h->scaled || h->filter_tol > 0.0 || !has_tiled(h, false)) return 0;
+    const int64_t P = static_cast<int64_t>(h->N) * (h->N + 1) / 2;
+    if (h->N > kResidentMaxSites || h->n_ados * P > kResidentMaxItems) return 0;
+    const int b = resident_lds_bytes(h->N, h->M, h->n_ados);
+    if (b > kResidentMaxLds) return 0;
+    bytes = std::max(bytes, b);
+  }
+  return bytes;
+}
+
 // Where the device data of one call live: each instance's regions (offsets
 // relative to its own base), the headers that identify the runs held there,
 // and the descriptor array and work list of the launch.
@@ -703,11 +742,59 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     return HEOM_OK;
   };
 
+  // End of a run: the last records, then the final sink populations.
+  auto finish = [&]() -> int {
+    if (want_rho) {
+      int rc = drain();
+      if (rc) return rc;
+    }
+    std::vector<double> sc(static_cast<size_t>(kScalars) * n);
+    bool want_sinks = false;
+    for (int k = 0; sinks_outs && k < n; ++k) want_sinks = want_sinks || sinks_outs[k] != nullptr;
+    if (want_sinks)
+      for (int k = 0; k < n; ++k)
+        if (sinks_outs[k])
+          HEOM_HIP(hipMemcpyAsync(sc.data() + kScalars * k, place.base[k] + place.inst[k].sc_y,
+                                  sizeof(double) * kScalars, hipMemcpyDeviceToHost, stream),
+                   "hipMemcpyAsync(scalars)");
+    HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    if (want_sinks)
+      for (int k = 0; k < n; ++k)
+        if (sinks_outs[k])
+          for (int q = 0; q < 3; ++q) sinks_outs[k][q] = sc[kScalars * k + q];
+    return HEOM_OK;
+  };
+
   if (want_rho) {
     HEOM_HIP(launch_snapshot(mixed, d_descs, n, slot, stream), "snapshot kernel");
     ++slot;
   }
   const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
+  // Small hierarchies: every step of a chunk in one launch of the resident
+  // kernel, one workgroup per instance, records written in place.
+  const int res_bytes = resident_bytes(hs, n, mixed, flags, opt.n_halo > 0 || opt.shard);
+  if (res_bytes > 0) {
+    HEOM_HIP(prepare_resident(res_bytes), "resident kernel attributes");
+    int64_t step = 0;
+    while (step < n_steps) {
+      int64_t run = std::min(n_steps - step, kResidentChunkSteps);
+      if (want_rho) {
+        // Records that fit the ring before the next drain.
+        const int64_t room = kRingRecords - slot;
+        run = std::min(run, (step / record_every + room) * record_every - step);
+      }
+      HEOM_HIP(launch_resident(d_descs, n, step, run, want_rho ? record_every : 0,
+                               static_cast<int>(slot), dt_fs, res_bytes, stream),
+               "resident kernel");
+      if (want_rho) slot += static_cast<int>((step + run) / record_every - step / record_every);
+      step += run;
+      if (want_rho && slot == kRingRecords) {
+        int rc = drain();
+        if (rc) return rc;
+      }
+    }
+    return finish();
+  }
   // Launch shape and store policy of each tile group: forced by the flags,
   // the defaults (plain stores), or the autotuner's.  A store policy forced
   // by the flags overrides the tuner's.  The tuner times repeated stage
@@ -841,26 +928,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
       }
     }
   }
-  if (want_rho) {
-    int rc = drain();
-    if (rc) return rc;
-  }
-  // Final sink populations.
-  std::vector<double> sc(static_cast<size_t>(kScalars) * n);
-  bool want_sinks = false;
-  for (int k = 0; sinks_outs && k < n; ++k) want_sinks = want_sinks || sinks_outs[k] != nullptr;
-  if (want_sinks)
-    for (int k = 0; k < n; ++k)
-      if (sinks_outs[k])
-        HEOM_HIP(hipMemcpyAsync(sc.data() + kScalars * k, place.base[k] + place.inst[k].sc_y,
-                                sizeof(double) * kScalars, hipMemcpyDeviceToHost, stream),
-                 "hipMemcpyAsync(scalars)");
-  HEOM_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
-  if (want_sinks)
-    for (int k = 0; k < n; ++k)
-      if (sinks_outs[k])
-        for (int q = 0; q < 3; ++q) sinks_outs[k][q] = sc[kScalars * k + q];
-  return HEOM_OK;
+  return finish();
 }
 
 Header header_for(heom_hierarchy *const *hs, int n, int precision) {
@@ -877,7 +945,7 @@ int propagate_impl(heom_hierarchy *const *hs, int n, int precision, int flags,
   int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, record_every,
                         HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
                             HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
-                            kShapeFlagMask);
+                            HEOM_NO_RESIDENT | kShapeFlagMask);
   if (rc) return rc;
   const Layout L = make_layout(hs, n, precision);
   if (!d_ws) return fail(HEOM_E_WORKSPACE, "workspace is NULL");
@@ -925,7 +993,7 @@ int advance_slots_impl(heom_hierarchy *const *hs, int n, int precision, int flag
   int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, 1,
                         HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
                             HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
-                            kShapeFlagMask);
+                            HEOM_NO_RESIDENT | kShapeFlagMask);
   if (rc) return rc;
   if (!d_workspaces || !workspace_bytes || !start)
     return fail(HEOM_E_INVALID, "workspaces, sizes and start flags are required");
@@ -1384,7 +1452,7 @@ int heom_propagate_sharded(heom_shard *s, int precision, int flags, const double
     int rc = check_common(hs, n, precision, flags, dt_fs, n_steps, record_every,
                           HEOM_RESUME | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL | HEOM_NO_GRAPH |
                               HEOM_NO_AUTOTUNE | HEOM_STREAMING_STORES | HEOM_PLAIN_STORES |
-                              kShapeFlagMask);
+                              HEOM_NO_RESIDENT | kShapeFlagMask);
     if (rc) return rc;
     const ShardLayout S = shard_layout(s, precision);
     if (!d_workspace) return fail(HEOM_E_WORKSPACE, "workspace is NULL");

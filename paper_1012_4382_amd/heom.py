@@ -33,7 +33,12 @@ HEOM_NO_GRAPH = 8
 HEOM_NO_AUTOTUNE = 16
 HEOM_STREAMING_STORES = 32
 HEOM_PLAIN_STORES = 64
-KERNELS = {"auto": 0, "generic": HEOM_GENERIC_KERNEL, "lane": HEOM_LANE_KERNEL}
+HEOM_NO_RESIDENT = 128
+# "auto": the resident kernel where a run fits it, else the LDS-tiled stage
+# kernels; "tiled": the stage kernels even there; "lane" / "generic": the
+# diagnostic kernels.
+KERNELS = {"auto": 0, "tiled": HEOM_NO_RESIDENT, "generic": HEOM_GENERIC_KERNEL,
+           "lane": HEOM_LANE_KERNEL}
 STORES = {None: 0, "streaming": HEOM_STREAMING_STORES, "plain": HEOM_PLAIN_STORES}
 
 

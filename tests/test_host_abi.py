@@ -134,7 +134,7 @@ def test_propagate_validation_errors_need_no_device():
                                   None, None)
 
     assert call(prec=7) == heom.HEOM_E_UNSUPPORTED
-    assert call(flags=128) == heom.HEOM_E_INVALID  # unknown flag
+    assert call(flags=1 << 13) == heom.HEOM_E_INVALID  # unknown flag
     assert call(flags=heom.HEOM_STREAMING_STORES | heom.HEOM_PLAIN_STORES) == heom.HEOM_E_INVALID
     assert call(dt=0.0) == heom.HEOM_E_INVALID
     assert call(dt=float("nan")) == heom.HEOM_E_INVALID
