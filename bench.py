@@ -566,13 +566,18 @@ def _scaled_filtered(heom, torch, workloads, stream, depths=(12, 16), tols=(1e-6
                 reach = nxt
             tiles_nz = int(np.unique(np.nonzero(nz)[0] // 64).size)
             tiles_reach = int(np.unique(np.nonzero(reach)[0] // 64).size)
+            # The same for the wide kernel's 16-ADO tiles.
+            t16_nz = int(np.unique(np.nonzero(nz)[0] // 16).size)
+            t16_reach = int(np.unique(np.nonzero(reach)[0] // 16).size)
             del sig, ws
             entry = {"filter_tol": tol, "eta": float(sk[0]),
                      "abs_eta_error_vs_plain": abs(float(sk[0]) - float(s0[0])),
                      "ados_nonzero_at_end": kept, "kept_fraction": kept / h.n_ados,
                      "nonzero_by_tier": by_tier, "tiles": (h.n_ados + 63) // 64,
                      "tiles_nonzero": tiles_nz, "tiles_within_4_links": tiles_reach,
-                     "seconds": el}
+                     "tiles16": (h.n_ados + 15) // 16, "tiles16_nonzero": t16_nz,
+                     "tiles16_within_4_links": t16_reach, "seconds": el}
+
             row["filtered"].append(entry)
             h.close()
         out["rows"].append(row)

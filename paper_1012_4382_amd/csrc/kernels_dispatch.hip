@@ -251,9 +251,9 @@ hipError_t launch_filter(bool mixed, const InstDesc *descs, const WorkItem *work
                          hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   if (mixed)
-    hipLaunchKernelGGL(filter_ados<float>, dim3(n_items), dim3(256), 0, stream, descs, work);
+    hipLaunchKernelGGL(filter_ados<float>, dim3(n_items), dim3(64), 0, stream, descs, work);
   else
-    hipLaunchKernelGGL(filter_ados<double>, dim3(n_items), dim3(256), 0, stream, descs, work);
+    hipLaunchKernelGGL(filter_ados<double>, dim3(n_items), dim3(64), 0, stream, descs, work);
   return hipGetLastError();
 }
 

@@ -1548,10 +1548,11 @@ __global__ void __launch_bounds__(256) halo_fill(const InstDesc *__restrict__ de
 }
 
 // The filter of a scaled hierarchy, after the last stage of a step: every ADO
-// n != 0 (one lane each) whose stored reals are all below the instance's
-// threshold in absolute value is set to zero in the state.
+// n != 0 (one lane each, one workgroup per 64-ADO work item) whose stored
+// reals are all below the instance's threshold in absolute value is set to
+// zero in the state.
 template <typename T>
-__global__ void __launch_bounds__(256) filter_ados(const InstDesc *__restrict__ descs,
+__global__ void __launch_bounds__(64) filter_ados(const InstDesc *__restrict__ descs,
                                                    const WorkItem *__restrict__ work) {
   const WorkItem w = work[blockIdx.x];
   const InstDesc &d = descs[w.inst];

@@ -221,7 +221,7 @@ def test_tile_shapes_and_forced_shape_validation():
     assert call(heom.tile_shape_flag(1)) == heom.HEOM_E_UNSUPPORTED
     assert "not built" in lib.heom_last_error().decode()
     assert call(heom.tile_shape_flag(count)) == heom.HEOM_E_INVALID
-    assert call(1 << 12) == heom.HEOM_E_INVALID
+    assert call(1 << 13) == heom.HEOM_E_INVALID
 
 
 @pytest.mark.parametrize("N,K,D,G", [(7, 0, 8, 8), (7, 1, 4, 3), (3, 0, 12, 5), (7, 0, 16, 8)])
