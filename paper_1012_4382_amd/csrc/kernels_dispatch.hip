@@ -9,45 +9,45 @@
 
 namespace heom {
 
-typedef StageKernel (*TilePart)(int N, int KP, bool mixed, bool streaming);
+typedef StageKernel (*TilePart)(int N, int KP, bool mixed, bool streaming, bool scaled);
 // Tile instances by shape and storage precision (_f1: FP64, _f0: FP32-mixed):
 // N <= 8 in every shape, N = 9..12 in shape 0 only.
-StageKernel tile_kernel_part_small_s0_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s0_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s0_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s0_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s0_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s0_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_9_10_s0_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_9_10_s0_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_11_s0_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_11_s0_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_12_s0_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_12_s0_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s1_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s1_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s1_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s1_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s1_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s1_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s2_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s2_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s2_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s2_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s2_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s2_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s3_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s3_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s3_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s3_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s3_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s3_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s4_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_small_s4_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s4_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_7_s4_f0(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s4_f1(int, int, bool, bool);
-StageKernel tile_kernel_part_8_s4_f0(int, int, bool, bool);
+StageKernel tile_kernel_part_small_s0_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s0_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s0_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s0_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s0_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s0_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_9_10_s0_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_9_10_s0_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_11_s0_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_11_s0_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_12_s0_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_12_s0_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s1_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s1_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s1_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s1_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s1_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s1_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s2_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s2_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s2_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s2_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s2_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s2_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s3_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s3_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s3_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s3_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s3_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s3_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s4_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_small_s4_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s4_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_7_s4_f0(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s4_f1(int, int, bool, bool, bool);
+StageKernel tile_kernel_part_8_s4_f0(int, int, bool, bool, bool);
 StageKernel lane_kernel_ptr(int N, int KP, bool mixed);
 
 namespace {
@@ -72,10 +72,11 @@ constexpr TilePart kTileParts[kTileShapes][12] = {
      nullptr, nullptr, nullptr, nullptr, nullptr},
 };
 
-StageKernel tile_kernel(int N, int KP, bool mixed, int shape, bool streaming = false) {
+StageKernel tile_kernel(int N, int KP, bool mixed, int shape, bool streaming = false,
+                        bool scaled = false) {
   if (shape < 0 || shape >= kTileShapes) return nullptr;
   for (TilePart part : kTileParts[shape]) {
-    StageKernel k = part ? part(N, KP, mixed, streaming) : nullptr;
+    StageKernel k = part ? part(N, KP, mixed, streaming, scaled) : nullptr;
     if (k) return k;
   }
   return nullptr;
@@ -90,6 +91,12 @@ bool has_streaming_stores(int N, int KP, bool mixed, int shape) {
 bool has_fixed_kernel(int N, int KP) { return lane_kernel_ptr(N, KP, false) != nullptr; }
 
 bool has_tile_kernel(int N, int KP) { return tile_kernel(N, KP, false, 0) != nullptr; }
+
+// Whether the tile kernel runs scaled hierarchies of (N, K+1) (shape 0, plain
+// stores: the one scaled instance).
+bool has_scaled_tile_kernel(int N, int KP, bool mixed) {
+  return tile_kernel(N, KP, mixed, 0, false, true) != nullptr;
+}
 
 // The wide kernel's LDS (tile, Hamiltonian, tables, and for scaled
 // hierarchies `levels` weights per mode) must fit the 160 KB of a gfx950 CU.
@@ -193,11 +200,13 @@ hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                        hist_slot);
     return hipGetLastError();
   }
-  if (levels > 0) return hipErrorInvalidValue;  // scaled: the wide kernel only
   StageKernel k = nullptr;
+  if (levels > 0 && kind != KernelKind::kTile) return hipErrorInvalidValue;
   switch (kind) {
     case KernelKind::kTile:
-      k = tile_kernel(N, KP, mixed, shape, streaming);
+      // Scaled hierarchies: shape 0 with plain stores only.
+      k = levels > 0 ? tile_kernel(N, KP, mixed, shape, false, true)
+                     : tile_kernel(N, KP, mixed, shape, streaming);
       break;
     case KernelKind::kLane:
       k = lane_kernel_ptr(N, KP, mixed);

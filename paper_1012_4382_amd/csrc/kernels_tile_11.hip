@@ -7,10 +7,11 @@
 
 namespace heom {
 
-StageKernel HEOM_SHAPED(tile_kernel_part_11)(int N, int KP, bool mixed, bool streaming) {
+StageKernel HEOM_SHAPED(tile_kernel_part_11)(int N, int KP, bool mixed, bool streaming,
+                                             bool scaled) {
   constexpr int S = HEOM_SHAPE;
   if (N == 11 && KP == 1)
-    return tile_instance<11, 1, S>(mixed, streaming);
+    return tile_instance<11, 1, S>(mixed, streaming, scaled);
   return nullptr;
 }
 

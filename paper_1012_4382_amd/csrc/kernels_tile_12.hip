@@ -7,10 +7,11 @@
 
 namespace heom {
 
-StageKernel HEOM_SHAPED(tile_kernel_part_12)(int N, int KP, bool mixed, bool streaming) {
+StageKernel HEOM_SHAPED(tile_kernel_part_12)(int N, int KP, bool mixed, bool streaming,
+                                             bool scaled) {
   constexpr int S = HEOM_SHAPE;
   if (N == 12 && KP == 1)
-    return tile_instance<12, 1, S>(mixed, streaming);
+    return tile_instance<12, 1, S>(mixed, streaming, scaled);
   return nullptr;
 }
 

@@ -7,12 +7,13 @@
 
 namespace heom {
 
-StageKernel HEOM_SHAPED(tile_kernel_part_8)(int N, int KP, bool mixed, bool streaming) {
+StageKernel HEOM_SHAPED(tile_kernel_part_8)(int N, int KP, bool mixed, bool streaming,
+                                            bool scaled) {
   constexpr int S = HEOM_SHAPE;
   if (N == 8 && KP == 1)
-    return tile_instance<8, 1, S>(mixed, streaming);
+    return tile_instance<8, 1, S>(mixed, streaming, scaled);
   if (N == 8 && KP == 2)
-    return tile_instance<8, 2, S>(mixed, streaming);
+    return tile_instance<8, 2, S>(mixed, streaming, scaled);
   return nullptr;
 }
 

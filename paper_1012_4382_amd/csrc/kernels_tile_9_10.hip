@@ -7,12 +7,13 @@
 
 namespace heom {
 
-StageKernel HEOM_SHAPED(tile_kernel_part_9_10)(int N, int KP, bool mixed, bool streaming) {
+StageKernel HEOM_SHAPED(tile_kernel_part_9_10)(int N, int KP, bool mixed, bool streaming,
+                                               bool scaled) {
   constexpr int S = HEOM_SHAPE;
   if (N == 9 && KP == 1)
-    return tile_instance<9, 1, S>(mixed, streaming);
+    return tile_instance<9, 1, S>(mixed, streaming, scaled);
   if (N == 10 && KP == 1)
-    return tile_instance<10, 1, S>(mixed, streaming);
+    return tile_instance<10, 1, S>(mixed, streaming, scaled);
   return nullptr;
 }
 

@@ -26,6 +26,7 @@ namespace heom {
 bool has_fixed_kernel(int N, int KP);
 hipError_t prepare_wide(int N, int M, bool mixed, int levels);
 bool has_wide_kernel(int N, int M, bool mixed, int levels);
+bool has_scaled_tile_kernel(int N, int KP, bool mixed);
 hipError_t launch_stage(KernelKind kind, bool mixed, int N, int KP, int shape,
                         const InstDesc *descs, const WorkItem *work, int n_items, int block,
                         int stage, double coef, int hist_slot, bool streaming, int levels,
@@ -360,7 +361,8 @@ struct Group {
 // for the wide kernel, whose loads use 32-bit byte offsets from the buffer
 // bases, state buffers below 4 GiB.
 bool shape_ok(const heom_hierarchy *h, bool mixed, int s) {
-  if (h->scaled) {  // the wide kernel only, with its weight tables in LDS
+  if (h->scaled) {  // tile shape 0 or the wide kernel (with its weight tables in LDS)
+    if (s == 0) return has_scaled_tile_kernel(h->N, h->KP, mixed);
     if (s != kWideShape || !has_wide_kernel(h->N, h->M, mixed, weight_levels(h))) return false;
   } else if (!tile_shape_info(h->N, h->KP, mixed, s, nullptr, nullptr, nullptr, nullptr,
                               nullptr)) {
@@ -465,16 +467,20 @@ int check_common(heom_hierarchy *const *hs, int n, int precision, int flags, dou
   for (int k = 0; k < n; ++k)
     if (hs[k]->scaled) {
       if (flags & (HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL))
-        return fail(HEOM_E_UNSUPPORTED, "scaled hierarchies run on the LDS-tiled wide kernel only");
-      if (!shape_ok(hs[k], mixed, kWideShape))
+        return fail(HEOM_E_UNSUPPORTED, "scaled hierarchies run on the LDS-tiled kernels only");
+      if (!shape_ok(hs[k], mixed, 0) && !shape_ok(hs[k], mixed, kWideShape))
         return fail(HEOM_E_UNSUPPORTED,
-                    "scaled hierarchies need the wide kernel: real H, N <= 32, K + 1 <= 4, "
-                    "its LDS within 160 KB and state buffers below 4 GiB");
+                    "scaled hierarchies need the tile kernel (N <= 12, K + 1 <= 2) or the wide "
+                    "kernel (real H, N <= 32, K + 1 <= 4, its LDS within 160 KB and state "
+                    "buffers below 4 GiB)");
+      if (forced >= 0 && !shape_ok(hs[k], mixed, forced))
+        return fail(HEOM_E_UNSUPPORTED, "scaled hierarchies run in tile launch shape 0 or " +
+                                            std::to_string(kWideShape) + " only");
     }
   if (forced >= 0 && !(flags & (HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)))
     for (int k = 0; k < n; ++k) {
       const heom_hierarchy *h = hs[k];
-      if (h->scaled) continue;  // always the wide kernel
+      if (h->scaled) continue;  // checked above
       if (h->h_real && has_tiled(h, mixed) && !shape_ok(h, mixed, forced))
         return fail(HEOM_E_UNSUPPORTED, "tile launch shape " + std::to_string(forced) +
                                             " is not built for N=" + std::to_string(h->N) +
@@ -571,7 +577,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     const heom_hierarchy *h = hs[k];
     KernelKind kind = KernelKind::kGeneric;
     if (h->scaled) {
-      kind = KernelKind::kTile;  // validated by check_common: the wide kernel
+      kind = KernelKind::kTile;  // validated by check_common: tile shape 0 or wide
     } else if (!(flags & HEOM_GENERIC_KERNEL) && h->h_real) {
       if (flags & HEOM_LANE_KERNEL) {
         if (has_fixed_kernel(h->N, h->KP)) kind = KernelKind::kLane;
@@ -804,7 +810,10 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   // buffers they leave behind before reading them, so the run is unchanged.
   for (Group &g : groups) {
     if (g.kind != KernelKind::kTile) continue;
-    int shape = g.levels > 0 ? kWideShape : forced_shape(flags);  // validated by check_common
+    // Scaled groups: the forced shape, else tile shape 0 where every member
+    // has it, else the wide kernel (no tuning; validated by check_common).
+    int shape = forced_shape(flags);
+    if (g.levels > 0 && shape < 0) shape = g.shape;
     bool streaming = false;
     if (shape < 0 && ((flags & HEOM_NO_AUTOTUNE) || n_steps == 0)) shape = g.shape;
     if (shape < 0 && opt.no_alloc) {
@@ -860,7 +869,7 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     }
     if (forced_streaming(flags) >= 0) streaming = forced_streaming(flags) == 1;
     g.shape = shape;
-    g.streaming = streaming && has_streaming_stores(g.N, g.KP, mixed, shape);
+    g.streaming = streaming && g.levels == 0 && has_streaming_stores(g.N, g.KP, mixed, shape);
     tile_shape_info(g.N, g.KP, mixed, shape, nullptr, &g.threads, nullptr, nullptr, nullptr);
   }
   // Enqueues one RK4 step (4 stages x kernel groups) on stream `s`.  With

@@ -675,6 +675,10 @@ struct TileCtx {
   int64_t S, i;
   int lane;
   double damp, coef;
+  // Scaled hierarchies: the coupling weights by mode and occupation, up then
+  // down ([M][levels] each, after the parameter block).
+  const double *wu, *wd;
+  int levels;
 };
 
 // Parameter q in the arithmetic type C: FP32 arithmetic reads the FP32 copy
@@ -696,6 +700,7 @@ struct ElemLoads {
   C yar[KP], yai[KP], ybr[KP], ybi[KP];  // deeper neighbours
   C zar[KP], zai[KP], zbr[KP], zbi[KP];  // shallower neighbours
   C str, sti;                            // state
+  C wua[KP], wub[KP], wda[KP], wdb[KP];  // scaled: coupling weights of the modes
 };
 
 // Phase 1 of element (A, B): issue every global load.  Neighbour gathers are
@@ -703,7 +708,7 @@ struct ElemLoads {
 // is weighted by zero (the occupation is zero exactly where the shallower
 // neighbour is missing), so the loads of all elements of a wave are in
 // flight together.
-template <int N, int KP, int A, int B, typename C, typename T>
+template <int N, int KP, int A, int B, typename C, typename T, bool SCALED>
 __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> &L) {
   constexpr int E = ent_re(N, A, B);
   const int lane = c.lane;
@@ -738,11 +743,24 @@ __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> 
   const uint32_t oi = self * sizeof(T);
   L.str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
   if constexpr (A != B) L.sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
+  if constexpr (SCALED) {
+    // Weights of the couplings along the modes of sites A and B, by the
+    // ADO's occupation of each mode (loaded with the gathers).
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int ma = A * KP + k, mb = B * KP + k;
+      const int oa = c.socc[ma * kTile + lane], ob = c.socc[mb * kTile + lane];
+      L.wua[k] = static_cast<C>(c.wu[ma * c.levels + oa]);
+      L.wub[k] = static_cast<C>(c.wu[mb * c.levels + ob]);
+      L.wda[k] = static_cast<C>(c.wd[ma * c.levels + oa]);
+      L.wdb[k] = static_cast<C>(c.wd[mb * c.levels + ob]);
+    }
+  }
 }
 
 // Phase 2 of element (A, B): right-hand side from the LDS tile and the loaded
 // values, RK4 stage update, store.  C is the arithmetic type.
-template <int N, int KP, int A, int B, typename C, typename T, bool STREAM>
+template <int N, int KP, int A, int B, typename C, typename T, bool STREAM, bool SCALED>
 __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads<C, KP> &L) {
 #pragma clang fp contract(off)
   constexpr int M = N * KP;
@@ -776,15 +794,25 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
     const int mb = B * KP + k;
     if constexpr (A != B) {
       // Deeper neighbours: + i Y (mode of site A) - i Y (mode of site B),
-      // weighted by zero where the neighbour is missing.
-      const C fa = c.sup[ma * kTile + lane] >= 0 ? C(1) : C(0);
-      const C fb = c.sup[mb * kTile + lane] >= 0 ? C(1) : C(0);
+      // weighted by zero where the neighbour is missing (scaled: by the
+      // coupling weight where it exists).
+      C fa = c.sup[ma * kTile + lane] >= 0 ? C(1) : C(0);
+      C fb = c.sup[mb * kTile + lane] >= 0 ? C(1) : C(0);
+      if constexpr (SCALED) {
+        fa = c.sup[ma * kTile + lane] >= 0 ? L.wua[k] : C(0);
+        fb = c.sup[mb * kTile + lane] >= 0 ? L.wub[k] : C(0);
+      }
       ar = fmad(-fa, L.yai[k], fmad(fb, L.ybi[k], ar));
       ai = fmad(-fb, L.ybr[k], fmad(fa, L.yar[k], ai));
     }
-    // Shallower neighbours: + i n c Z (site A) - i n conj(c) Z (site B).
-    const C na = static_cast<C>(c.socc[ma * kTile + lane]);
-    const C nb = static_cast<C>(c.socc[mb * kTile + lane]);
+    // Shallower neighbours: + i n c Z (site A) - i n conj(c) Z (site B)
+    // (scaled: the down weight in place of n).
+    C na = static_cast<C>(c.socc[ma * kTile + lane]);
+    C nb = static_cast<C>(c.socc[mb * kTile + lane]);
+    if constexpr (SCALED) {
+      na = L.wda[k];
+      nb = L.wdb[k];
+    }
     const C car = na * par<C>(c, o_cr + ma), cai = na * par<C>(c, o_ci + ma);
     const C cbr = nb * par<C>(c, o_cr + mb), cbi = nb * par<C>(c, o_ci + mb);
     const C zai = (A == B) ? C(0) : L.zai[k];
@@ -810,17 +838,20 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
 
 // One chunk of wave G's elements (element indices OFF + K): all global loads
 // first, then arithmetic and stores.
-template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool STREAM, int... K>
+template <int N, int KP, int G, int W, int OFF, typename C, typename T, bool STREAM, bool SCALED,
+          int... K>
 __device__ __forceinline__ void tile_chunk(const TileCtx<T> &c, std::integer_sequence<int, K...>) {
   ElemLoads<C, KP> L[sizeof...(K)];
-  (tile_load<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T>(c, L[K]),
-   ...);
-  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, STREAM>(
+  (tile_load<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, SCALED>(
        c, L[K]),
+   ...);
+  (tile_finish<N, KP, elem_a(N, G + (OFF + K) * W), elem_b(N, G + (OFF + K) * W), C, T, STREAM,
+               SCALED>(c, L[K]),
    ...);
 }
 
-template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T, bool STREAM>
+template <int N, int KP, int G, int W, int CH0, int OFF, typename C, typename T, bool STREAM,
+          bool SCALED>
 __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int P = N * (N + 1) / 2;
   constexpr int count = (P - G + W - 1) / W;
@@ -829,25 +860,26 @@ __device__ __forceinline__ void tile_chunks(const TileCtx<T> &c) {
   constexpr int CH = CH0 / KP > 0 ? CH0 / KP : 1;
   if constexpr (OFF < count) {
     constexpr int len = (count - OFF < CH) ? count - OFF : CH;
-    tile_chunk<N, KP, G, W, OFF, C, T, STREAM>(c, std::make_integer_sequence<int, len>{});
+    tile_chunk<N, KP, G, W, OFF, C, T, STREAM, SCALED>(c, std::make_integer_sequence<int, len>{});
     // Keep the next chunk's LDS reads from being hoisted above this chunk
     // (they cannot alias its global stores), which would hold every operand
     // of the wave's elements in registers at once.
 #if HEOM_TILE_CHUNK_BARRIER
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T, STREAM>(c);
+    tile_chunks<N, KP, G, W, CH0, OFF + CH, C, T, STREAM, SCALED>(c);
   }
 }
 
 // Elements G, G + W, ... of every ADO of the tile (wave G of W).
-template <int N, int KP, int W, int CH0, typename C, typename T, bool STREAM, int G = 0>
+template <int N, int KP, int W, int CH0, typename C, typename T, bool STREAM, bool SCALED,
+          int G = 0>
 __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
   if constexpr (G < W) {
     if (wave == G)
-      tile_chunks<N, KP, G, W, CH0, 0, C, T, STREAM>(c);
+      tile_chunks<N, KP, G, W, CH0, 0, C, T, STREAM, SCALED>(c);
     else
-      tile_dispatch<N, KP, W, CH0, C, T, STREAM, G + 1>(wave, c);
+      tile_dispatch<N, KP, W, CH0, C, T, STREAM, SCALED, G + 1>(wave, c);
   }
 }
 
@@ -860,7 +892,7 @@ __device__ __forceinline__ void tile_dispatch(int wave, const TileCtx<T> &c) {
 // sigma_0, in both the FP64 copy and the FP32 planes.  Keeping this pass out
 // of the unrolled element code keeps FP64 operands out of the register
 // allocation of the FP32 kernel.
-template <int N, int KP, typename T>
+template <int N, int KP, typename T, bool SCALED>
 __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
 #pragma clang fp contract(off)
   constexpr int M = N * KP;
@@ -926,13 +958,21 @@ __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
   for (int k = 0; k < KP; ++k) {
     const int ma = A * KP + k, mb = B * KP + k;
     if (off) {
-      const double fa = c.sup[ma * kTile] >= 0 ? 1.0 : 0.0;
-      const double fb = c.sup[mb * kTile] >= 0 ? 1.0 : 0.0;
+      double fa = c.sup[ma * kTile] >= 0 ? 1.0 : 0.0;
+      double fb = c.sup[mb * kTile] >= 0 ? 1.0 : 0.0;
+      if constexpr (SCALED) {
+        fa = c.sup[ma * kTile] >= 0 ? c.wu[ma * c.levels + c.socc[ma * kTile]] : 0.0;
+        fb = c.sup[mb * kTile] >= 0 ? c.wu[mb * c.levels + c.socc[mb * kTile]] : 0.0;
+      }
       ar = fmad(-fa, yai[k], fmad(fb, ybi[k], ar));
       ai = fmad(-fb, ybr[k], fmad(fa, yar[k], ai));
     }
-    const double na = static_cast<double>(c.socc[ma * kTile]);
-    const double nb = static_cast<double>(c.socc[mb * kTile]);
+    double na = static_cast<double>(c.socc[ma * kTile]);
+    double nb = static_cast<double>(c.socc[mb * kTile]);
+    if constexpr (SCALED) {
+      na = c.wd[ma * c.levels + c.socc[ma * kTile]];
+      nb = c.wd[mb * c.levels + c.socc[mb * kTile]];
+    }
     const double car = na * c.P[o_cr + ma], cai = na * c.P[o_ci + ma];
     const double cbr = nb * c.P[o_cr + mb], cbi = nb * c.P[o_ci + mb];
     ar = fmad(-car, zai[k], fmad(-cai, zar[k], ar));
@@ -950,7 +990,7 @@ __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
   }
 }
 
-template <int N, int KP, typename T, int SHAPE, bool STREAM>
+template <int N, int KP, typename T, int SHAPE, bool STREAM, bool SCALED>
 __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                                   tile_shape(sizeof(T) == 8, SHAPE).min_waves)
     stage_tile(const InstDesc *__restrict__ descs, const WorkItem *__restrict__ work, int stage,
@@ -1016,8 +1056,12 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                           0,
                           lane,
                           0.0,
-                          coef};
-      for (int p = threadIdx.x; p < N * (N + 1) / 2; p += blockDim.x) tile_sigma0<N, KP, T>(c0, p);
+                          coef,
+                          d.params + param_offsets(N, M).total,
+                          d.params + param_offsets(N, M).total + M * d.levels,
+                          d.levels};
+      for (int p = threadIdx.x; p < N * (N + 1) / 2; p += blockDim.x)
+        tile_sigma0<N, KP, T, SCALED>(c0, p);
       return;
     }
   }
@@ -1085,26 +1129,42 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
                  i,
                  lane,
                  0.0,
-                 coef};
+                 coef,
+                 d.params + param_offsets(N, M).total,
+                 d.params + param_offsets(N, M).total + M * d.levels,
+                 d.levels};
   if (!valid) return;  // no barrier below
 #pragma unroll
   for (int m = 0; m < M; ++m)
     ctx.damp = fmad(static_cast<double>(socc[m * kTile + lane]), P[2 * N * N + 4 * N + 2 * M + m],
                     ctx.damp);
-  tile_dispatch<N, KP, W, CH0, T, T, STREAM>(wave, ctx);
+  tile_dispatch<N, KP, W, CH0, T, T, STREAM, SCALED>(wave, ctx);
 }
 
-// The instance of a tile unit for storage `mixed` and the store policy: null
-// for the precision the unit is not compiled for (the other unit of the same
-// shape provides it), and for streaming stores in FP32-mixed storage (not
-// built: at most 1 % faster there, on small launches only).
+// The instance of a tile unit for storage `mixed`, the store policy and
+// scaled hierarchies: null for the precision the unit is not compiled for
+// (the other unit of the same shape provides it), for streaming stores in
+// FP32-mixed storage (not built: at most 1 % faster there, on small launches
+// only), and for scaled hierarchies outside shape 0 with plain stores (their
+// only instance).
 template <int N, int KP, int S>
-StageKernel tile_instance(bool mixed, bool streaming) {
+StageKernel tile_instance(bool mixed, bool streaming, bool scaled) {
 #if HEOM_TILE_F64
   if (mixed) return nullptr;
-  return streaming ? &stage_tile<N, KP, double, S, true> : &stage_tile<N, KP, double, S, false>;
+  if (scaled) {
+    if constexpr (S == 0)
+      return streaming ? nullptr : &stage_tile<N, KP, double, S, false, true>;
+    return nullptr;
+  }
+  return streaming ? &stage_tile<N, KP, double, S, true, false>
+                   : &stage_tile<N, KP, double, S, false, false>;
 #else
-  return mixed && !streaming ? &stage_tile<N, KP, float, S, false> : nullptr;
+  if (!mixed || streaming) return nullptr;
+  if (scaled) {
+    if constexpr (S == 0) return &stage_tile<N, KP, float, S, false, true>;
+    return nullptr;
+  }
+  return &stage_tile<N, KP, float, S, false, false>;
 #endif
 }
 

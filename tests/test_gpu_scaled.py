@@ -1,8 +1,9 @@
 """GPU: the scaled hierarchy and its filter against the oracle.
 
 The scaled hierarchy holds sigma_n / w_n with w_n = sqrt(prod_m n_m! |c_m|^n_m)
-(the introduction's scaled HEOM); its stages run on the wide kernel with
-coupling weights by mode and occupation.  The oracle propagates the same
+(the introduction's scaled HEOM); its stages run on the tile kernel (launch
+shape 0, N <= 12) or the wide kernel with coupling weights by mode and
+occupation, and the two agree bitwise.  The oracle propagates the same
 scaled equations (pinned in test_oracle_pins.py against the similarity
 transform of the dense generator and against the unscaled oracle).
 
@@ -72,6 +73,26 @@ def test_scaled_against_oracle(name):
     multi, _, _ = h.tables()
     perm = match_oracle_order(multi, oracle.enumerate_ados(sys_, depth))
     assert_tiers(multi, sig, ref["state"][0][perm], FP64_TOL, min_nonzero_tier=depth)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_scaled_tile_equals_wide(name, precision):
+    """Scaled hierarchies of N <= 12 run on the tile kernel by default; the
+    wide kernel (launch shape 5, forced) gives the same records, sinks and
+    state bitwise, with and without the filter."""
+    sys_, depth, rho0, steps = CASES[name]()
+    for tol in (0.0, 1e-7):
+        _say(f"case: scaled {name}, filter {tol:g}, tile vs wide kernel, {precision}")
+        h = heom.Hierarchy(sys_, depth, scaled=True, filter_tol=tol)
+        a = heom.propagate(h, rho0, 1.0, steps, record_every=10, precision=precision)
+        b = heom.propagate(h, rho0, 1.0, steps, record_every=10, precision=precision,
+                           tile_shape=5)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        sa, _ = heom.read_state(h, a[2], precision=precision)
+        sb, _ = heom.read_state(h, b[2], precision=precision)
+        assert np.array_equal(sa, sb)
+        h.close()
 
 
 def test_scaled_equals_unscaled_on_sigma0():
