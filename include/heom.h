@@ -167,6 +167,14 @@ int heom_hierarchy_tables(const heom_hierarchy *h, int32_t *multi, int32_t *up, 
 int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, double *c_im,
                          double *nu, double *delta);
 
+/* The largest time step (fs) at which every ADO's damping rate stays inside
+ * classic RK4's stability interval on the negative real axis, by the rule
+ * dt * max_n (sum_m n_m nu_m) <= 2.5: 2.5 / (depth * max_m nu_m), or +inf
+ * at depth 0.  A step above it is not refused (the Hamiltonian and the
+ * couplings also bound it, so it is a guide, not a guarantee); the Python
+ * binding warns when a call's dt exceeds it.  Appendix B: fixed-step RK4. */
+int heom_max_stable_dt(const heom_hierarchy *h, double *dt_fs);
+
 /* Propagates rho0 by n_steps RK4 steps of dt_fs on the current device.
  *   precision      HEOM_FP64 or HEOM_FP32_MIXED
  *   flags          HEOM_RESUME: continue the run held in d_workspace (rho0 is

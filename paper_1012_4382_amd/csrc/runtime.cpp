@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <string>
@@ -1199,6 +1200,15 @@ int heom_hierarchy_modes(const heom_hierarchy *h, int32_t *site, double *c_re, d
   }
   if (delta)
     for (int a = 0; a < h->N; ++a) delta[a] = h->delta[a];
+  return HEOM_OK;
+}
+
+int heom_max_stable_dt(const heom_hierarchy *h, double *dt_fs) {
+  if (!h || !dt_fs) return fail(HEOM_E_INVALID, "hierarchy or output is NULL");
+  double nu_max = 0.0;
+  for (int m = 0; m < h->M; ++m) nu_max = std::max(nu_max, h->nu[m]);
+  const double rate = h->depth * nu_max;  // the deepest ADO on the fastest mode
+  *dt_fs = rate > 0.0 ? 2.5 / rate : std::numeric_limits<double>::infinity();
   return HEOM_OK;
 }
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import warnings
 
 import numpy as np
 
@@ -40,6 +41,17 @@ HEOM_NO_RESIDENT = 128
 KERNELS = {"auto": 0, "tiled": HEOM_NO_RESIDENT, "generic": HEOM_GENERIC_KERNEL,
            "lane": HEOM_LANE_KERNEL}
 STORES = {None: 0, "streaming": HEOM_STREAMING_STORES, "plain": HEOM_PLAIN_STORES}
+
+
+def _warn_dt(hs, dt_fs: float):
+    """Warns when dt exceeds a hierarchy's RK4 stability guide
+    (heom_max_stable_dt); the library does not refuse such a step."""
+    for h in hs:
+        if dt_fs > h.max_stable_dt_fs:
+            warnings.warn(f"dt = {dt_fs} fs exceeds the RK4 stability guide "
+                          f"{h.max_stable_dt_fs:.4g} fs of a depth-{h.depth} hierarchy "
+                          "(dt * max sum_m n_m nu_m > 2.5)", RuntimeWarning, stacklevel=3)
+            return
 
 
 def tile_shape_flag(shape: int) -> int:
@@ -116,6 +128,7 @@ _SIGNATURES = [
     ("heom_hierarchy_info", ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_sz), _P(_sz)]),
     ("heom_hierarchy_tables", ctypes.c_int, [_vp, _P(_i32), _P(_i32), _P(_i32)]),
     ("heom_hierarchy_modes", ctypes.c_int, [_vp, _P(_i32), _P(_d), _P(_d), _P(_d), _P(_d)]),
+    ("heom_max_stable_dt", ctypes.c_int, [_vp, _P(_d)]),
     ("heom_propagate", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _P(_d), _d, _i64, _i64, _vp,
                                       _sz, _vp, _P(_d), _P(_d)]),
     ("heom_batch_workspace_bytes", ctypes.c_int, [_P(_vp), _i32, ctypes.c_int, _P(_sz)]),
@@ -236,6 +249,9 @@ class Hierarchy:
         self.n_ados = n.value
         self.n_modes = m.value
         self.workspace_bytes = {HEOM_FP64: b64.value, HEOM_FP32_MIXED: b32.value}
+        dt = ctypes.c_double()
+        _check(library().heom_max_stable_dt(h, ctypes.byref(dt)), "heom_max_stable_dt")
+        self.max_stable_dt_fs = dt.value
 
     @property
     def handle(self):
@@ -297,6 +313,7 @@ def propagate(h: Hierarchy, rho0, dt_fs: float, n_steps: int, record_every: int 
     tile_shape forces a tile launch shape, autotune=False uses shape 0; stores
     "streaming" / "plain" forces the tile kernels' store policy).
     Returns (rho [records, N, N] complex | None, sinks [3], workspace)."""
+    _warn_dt([h], dt_fs)
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(h.workspace_bytes[prec])
@@ -328,6 +345,7 @@ def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1
                     kernel: str = "auto", want_rho: bool = True, graphs: bool = True,
                     tile_shape=None, autotune: bool = True, stores=None):
     """Runs heom_propagate_batch.  Returns (list of rho | None, sinks [n, 3], workspace)."""
+    _warn_dt(hs, dt_fs)
     n = len(hs)
     prec = PRECISIONS[precision]
     if workspace is None:
@@ -360,6 +378,7 @@ def propagate_batch(hs, rho0s, dt_fs: float, n_steps: int, record_every: int = 1
 
 def efficiency(h: Hierarchy, rho0, dt_fs: float, t_end_fs: float, pop_tol: float = 1e-5,
                precision="fp64", workspace=None, stream=None) -> dict:
+    _warn_dt([h], dt_fs)
     prec = PRECISIONS[precision]
     if workspace is None:
         workspace = allocate_workspace(h.workspace_bytes[prec])
@@ -428,6 +447,7 @@ def advance_slots(hs, workspaces, start, rho0s, dt_fs: float, n_steps: int, scra
     """Runs heom_advance_slots.  Returns (list of final rho [N, N] | None, sinks [n, 3]).
     Raises SlotsNumericError when some slots' results are non-finite (every
     slot was advanced), HeomError on any other failure."""
+    _warn_dt(hs, dt_fs)
     a, rhos, sinks = _slots_call(hs, workspaces, start, rho0s, want_rho)
     sptr, sbytes = _ws_args(scratch)
     flags = _flags(False, kernel, graphs, tile_shape, autotune, stores)
@@ -445,6 +465,7 @@ def advance_slots_noalloc(hs, workspaces, start, rho0s, dt_fs: float, n_steps: i
                           stores=None):
     """Runs heom_advance_slots_noalloc (no scratch argument; nothing is
     allocated on the device).  Returns and raises as advance_slots."""
+    _warn_dt(hs, dt_fs)
     a, rhos, sinks = _slots_call(hs, workspaces, start, rho0s, want_rho)
     flags = _flags(False, kernel, True, tile_shape, autotune, stores)
     status = library().heom_advance_slots_noalloc(a["arr"], len(hs), PRECISIONS[precision],
@@ -496,6 +517,7 @@ def propagate_sharded(s: Shard, rho0, dt_fs: float, n_steps: int, record_every: 
                       workspace=None, stream=None, resume: bool = False, kernel: str = "auto",
                       graphs: bool = True, tile_shape=None, autotune: bool = True, stores=None):
     """Runs heom_propagate_sharded (FP64).  Returns (rho [records, N, N], sinks [3], workspace)."""
+    _warn_dt([s.h], dt_fs)
     if workspace is None:
         workspace = allocate_workspace(s.workspace_bytes)
     ptr, nbytes = _ws_args(workspace)

@@ -10,9 +10,8 @@ are compared with the GPU runs in ``tests/test_gpu_goldens.py``:
   5000 RK4 steps of 1 fs (5 ps, eq:eta at t = 5 ps), FP64;
 * ``oracle_precision_depth8.npz`` -- the same generator at depth 8 (6435 ADOs),
   seeds 0 and 1, T = 77 K and 300 K, start at site 1, 5000 steps;
-* ``oracle_sweep_k1.npz`` -- the first 16 of the 64 parameter-sweep instances
-  (one Matsubara term per bath; depths 3, 4 and 5: 5, 4 and 7 of them), 1000
-  steps;
+* ``oracle_sweep_k1.npz`` -- all 64 parameter-sweep instances
+  (one Matsubara term per bath; depths 3, 4 and 5), 1000 steps;
 * ``oracle_serving.npz`` -- every request of the 200-request serving trace:
   at its full length where N <= 12 or depth 2; the 24-site requests at depth 3
   over their first 100 steps and at depth 4 over their first 50 steps (the
@@ -117,12 +116,23 @@ def make_precision(threads):
           steps=np.array(5000), pops=np.array(pops), rho=np.array(rho), scalars=np.array(sc))
 
 
-SWEEP_INSTANCES = 16
+SWEEP_INSTANCES = 64
 
 
 def make_sweep(threads):
-    rho, sc, depth = [], [], []
+    """Every instance of the sweep over 1000 steps, sigma_0 every 100 steps;
+    continues a partly written file (instances are written as they finish)."""
+    path = FILES["sweep"]
+    rho, sc, depth, done = [], [], [], []
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            done = [int(i) for i in z["instances"]]
+            rho = list(z["rho"])
+            sc = list(z["scalars"])
+            depth = [int(d) for d in z["depth"]]
     for i in range(SWEEP_INSTANCES):
+        if i in done:
+            continue
         t0 = time.perf_counter()
         w = workloads.sweep_instance(i)
         res = oracle.propagate(w["system"], w["depth"], w["rho0"], w["dt"], w["steps"],
@@ -130,11 +140,11 @@ def make_sweep(threads):
         rho.append(res["rho"].copy())
         sc.append(res["scalars"].copy())
         depth.append(w["depth"])
+        done.append(i)
+        _save(path, instances=np.array(done), depth=np.array(depth), steps=np.array(1000),
+              rho=np.array(rho), scalars=np.array(sc))
         print(f"sweep {i} depth {w['depth']}: P_trap {res['scalars'][0]:.12f} "
-              f"({time.perf_counter() - t0:.0f} s)", flush=True)
-    _save(FILES["sweep"], instances=np.arange(SWEEP_INSTANCES), depth=np.array(depth),
-          steps=np.array(1000),
-          rho=np.array(rho), scalars=np.array(sc))
+              f"({time.perf_counter() - t0:.0f} s, {len(done)} done)", flush=True)
 
 
 def make_serving(threads, n_requests=200):

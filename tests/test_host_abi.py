@@ -295,3 +295,22 @@ def test_scaled_hierarchy_build_and_validation():
         heom.Shard(heom.Hierarchy(workloads.fmo_like(seed=0, depth=5)["system"], 5,
                                   scaled=True), 2)
     assert e.value.status == heom.HEOM_E_UNSUPPORTED
+
+
+def test_max_stable_dt_guide_and_warning():
+    """heom_max_stable_dt: dt * depth * max nu_m = 2.5 for the deepest ADO on
+    the fastest mode (classic RK4's stability interval, Appendix B's fixed-step
+    RK4); +inf at depth 0; the binding warns above it and stays silent below."""
+    w = workloads.sweep_instance(2)  # one Matsubara term per bath: nu_1 >> gamma
+    h = heom.Hierarchy(w["system"], w["depth"])
+    _, _, nu, _ = h.modes()
+    assert h.max_stable_dt_fs == pytest.approx(2.5 / (w["depth"] * nu.max()), rel=1e-15)
+    assert heom.Hierarchy(w["system"], 0).max_stable_dt_fs == float("inf")
+    lib = heom.library()
+    assert lib.heom_max_stable_dt(None, None) == heom.HEOM_E_INVALID
+    with pytest.warns(RuntimeWarning, match="stability"):
+        heom._warn_dt([h], 1.01 * h.max_stable_dt_fs)
+    import warnings as _w
+    with _w.catch_warnings():
+        _w.simplefilter("error")
+        heom._warn_dt([h], 0.99 * h.max_stable_dt_fs)
