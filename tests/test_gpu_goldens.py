@@ -12,8 +12,8 @@ compares it with the oracle over the whole run:
   within 1e-5 absolute on populations (every 10 steps) and eta, FP64 within
   1e-10;
 * the 64-instance parameter sweep (one Matsubara term per bath, depth 3-5)
-  in one batched launch, 1000 steps, against the 16 instances the oracle
-  covers (all three depths), FP64 and FP32-mixed;
+  in one batched launch, 1000 steps, every instance against the oracle, FP64
+  and FP32-mixed;
 * served requests of the serving trace against the same request run alone
   (bitwise) and against the oracle (at full length where it covers it; the
   24-site requests at depth 3 and 4 over the oracle's first steps).
@@ -116,6 +116,7 @@ def test_sweep_batched_launch_64_instances(precision):
     rhos, sinks, _ = heom.propagate_batch(hs, [w["rho0"] for w in cases], 1.0, 1000,
                                           record_every=100, precision=precision)
     assert sorted({int(d) for d in g["depth"]}) == [3, 4, 5]
+    assert sorted(int(i) for i in g["instances"]) == list(range(64))
     for k, i in enumerate(g["instances"]):
         i = int(i)
         assert hs[i].depth == int(g["depth"][k])
@@ -126,8 +127,8 @@ def test_sweep_batched_launch_64_instances(precision):
         else:
             assert np.max(np.abs(_pops(rhos[i]) - _pops(g["rho"][k]))) <= FP32_TOL, i
             assert abs(sinks[i][0] - g["scalars"][k][0]) <= FP32_TOL, i
-    # Every instance (also those the oracle does not cover) conserves
-    # population exactly: Tr sigma_0 + P_trap + P_rec = 1.
+    # Every instance conserves population exactly: Tr sigma_0 + P_trap +
+    # P_rec = 1.
     for r, s in zip(rhos, sinks):
         assert abs(np.trace(r[-1]).real + s[0] + s[1] - 1.0) < (1e-12 if precision == "fp64"
                                                                 else 1e-6)
