@@ -75,12 +75,13 @@ enum {
                                without either, the autotuner's policy, or
                                plain stores where no tuning is done)            */
   HEOM_NO_RESIDENT = 128    /* diagnostic: launch every RK4 stage even where
-                               the run fits the resident kernel (FP64, real H,
-                               unscaled, N <= 4 and at most 1024 packed
-                               elements x ADOs per instance: all steps of a
+                               the run fits a resident kernel (all steps of a
                                chunk in one launch, one workgroup per instance,
-                               the hierarchy in LDS; results are bitwise the
-                               same)                                          */
+                               the hierarchy in LDS): FP64, real H, unscaled,
+                               and either every instance with the same N <= 8
+                               and K+1 <= 2 and at most 1024 (some shapes 2048)
+                               packed elements x ADOs, or N <= 4 and at most
+                               1024 of them; results are bitwise the same     */
 };
 /* Flag bits that force tile launch shape s (0 <= s < heom_tile_shape_count())
  * for every tile-kernel group of a call. */

@@ -161,26 +161,75 @@ hipError_t prepare_wide(int N, int M, bool mixed, int levels) {
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-// LDS bytes the resident kernel needs for an instance of n ADOs.
-int resident_lds_bytes(int N, int M, int64_t n_ados) {
-  return resident_lds(N, M, static_cast<int>(n_ados)).total;
+// LDS bytes the resident kernel needs for an instance of n ADOs: the
+// run-time-N kernel (fixed = false) or the compile-time one.
+int resident_lds_bytes(int N, int M, int64_t n_ados, bool fixed) {
+  const int n = static_cast<int>(n_ados);
+  return fixed ? fixed_lds_bytes(N, n) : resident_lds(N, M, n).total;
 }
 
-// Lets the resident kernel take `bytes` of dynamic LDS.
-hipError_t prepare_resident(int bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_resident),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+// The resident kernel with compile-time N, K+1 and items per thread R, or
+// nullptr where not built (N <= 8, K+1 <= 2, R <= 2; more items per thread
+// spill registers at every N).
+template <int N, int KP>
+const void *resident_fixed_r(int R) {
+  switch (R) {
+    case 1: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 1>);
+    case 2: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 2>);
+    default: return nullptr;
+  }
+}
+template <int KP>
+const void *resident_fixed_n(int N, int R) {
+  switch (N) {
+    case 1: return resident_fixed_r<1, KP>(R);
+    case 2: return resident_fixed_r<2, KP>(R);
+    case 3: return resident_fixed_r<3, KP>(R);
+    case 4: return resident_fixed_r<4, KP>(R);
+    case 5: return resident_fixed_r<5, KP>(R);
+    case 6: return resident_fixed_r<6, KP>(R);
+    case 7: return resident_fixed_r<7, KP>(R);
+    case 8: return resident_fixed_r<8, KP>(R);
+    default: return nullptr;
+  }
+}
+const void *resident_kernel(int N, int KP, int R) {
+  if (R == 0) return reinterpret_cast<const void *>(&stage_resident);
+  if (KP == 1) return resident_fixed_n<1>(N, R);
+  if (KP == 2) return resident_fixed_n<2>(N, R);
+  return nullptr;
+}
+
+// Whether the compile-time resident kernel for (N, K+1, R) is built and
+// keeps every value in registers (no scratch memory: a spilled operand would
+// cost a memory round trip per stage).
+bool resident_fixed_usable(int N, int KP, int R) {
+  const void *k = R > 0 ? resident_kernel(N, KP, R) : nullptr;
+  if (!k) return false;
+  hipFuncAttributes attr{};
+  if (hipFuncGetAttributes(&attr, k) != hipSuccess) return false;
+  return attr.localSizeBytes == 0;
+}
+
+// Lets the resident kernel (R = 0: run-time N; else the compile-time
+// instance for N, K+1 and R items per thread) take `bytes` of dynamic LDS.
+hipError_t prepare_resident(int N, int KP, int R, int bytes) {
+  const void *k = resident_kernel(N, KP, R);
+  if (!k) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // Steps step0 + 1 ... step0 + n_steps of n_inst resident instances, one
-// workgroup each (descs[0 .. n_inst - 1]).
-hipError_t launch_resident(const InstDesc *descs, int n_inst, int64_t step0, int64_t n_steps,
-                           int64_t record_every, int slot0, double dt, int lds_bytes,
-                           hipStream_t stream) {
-  hipLaunchKernelGGL(stage_resident, dim3(n_inst), dim3(kResidentThreads),
-                     static_cast<size_t>(lds_bytes), stream, descs, step0, n_steps, record_every,
-                     slot0, dt);
-  return hipGetLastError();
+// workgroup each (descs[0 .. n_inst - 1]), on the kernel prepare_resident
+// names for (N, KP, R).
+hipError_t launch_resident(int N, int KP, int R, const InstDesc *descs, int n_inst,
+                           int64_t step0, int64_t n_steps, int64_t record_every, int slot0,
+                           double dt, int lds_bytes, hipStream_t stream) {
+  const void *k = resident_kernel(N, KP, R);
+  if (!k) return hipErrorInvalidValue;
+  void *args[] = {&descs, &step0, &n_steps, &record_every, &slot0, &dt};
+  return hipLaunchKernel(k, dim3(n_inst), dim3(kResidentThreads), args,
+                         static_cast<size_t>(lds_bytes), stream);
 }
 
 // `streaming` selects the tile kernel instance with non-temporal output

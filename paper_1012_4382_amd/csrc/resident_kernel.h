@@ -9,9 +9,13 @@
 // history ring) and writes the state back.  This removes the launch floor of
 // about 5 us per stage that bounds a plain solve of a small hierarchy.
 //
-// Each packed element is computed with the operations of the tile kernel's
-// tile_finish, in its order (the same explicit fused multiply-adds, the same
-// zero weights for missing neighbours), so the two paths agree bitwise.
+// Two forms: stage_resident reads N and K+1 of each instance at run time (a
+// batch may mix hierarchies) and keeps the planes of the stage launches in
+// LDS; stage_resident_fixed is compiled per (N, K+1) and keeps full matrices,
+// so each thread's operands sit at fixed offsets (below).  Each packed
+// element is computed with the operations of the tile kernel's tile_finish,
+// in its order (the same explicit fused multiply-adds, the same zero weights
+// for missing neighbours), so every path agrees bitwise.
 //
 // Included after stage_kernels.h (fmad, ent_re, scalar_update_wave, ...).
 
@@ -138,128 +142,428 @@ __device__ __forceinline__ void resident_element(const ResidentCtx &c, int A, in
   if (offd) c.out[(E + 1) * n + i] = fmad(coef, ai, sti);
 }
 
+// Pointers into the LDS layout of one instance.
+struct ResidentView {
+  double *Y, *A, *B, *H, *hg, *dl, *tr, *rc, *cr, *ci, *damp, *sc;  // sc: [Y, A, B][kScalars]
+  int32_t *up, *dn;
+  uint8_t *occ, *pa, *pb;
+};
+__device__ __forceinline__ ResidentView resident_view(char *smem, const ResidentLds &L) {
+  ResidentView v;
+  v.Y = reinterpret_cast<double *>(smem + L.y);
+  v.A = reinterpret_cast<double *>(smem + L.a);
+  v.B = reinterpret_cast<double *>(smem + L.b);
+  v.H = reinterpret_cast<double *>(smem + L.h);
+  v.hg = reinterpret_cast<double *>(smem + L.hg);
+  v.dl = reinterpret_cast<double *>(smem + L.dl);
+  v.tr = reinterpret_cast<double *>(smem + L.tr);
+  v.rc = reinterpret_cast<double *>(smem + L.rc);
+  v.cr = reinterpret_cast<double *>(smem + L.cr);
+  v.ci = reinterpret_cast<double *>(smem + L.ci);
+  v.damp = reinterpret_cast<double *>(smem + L.damp);
+  v.sc = reinterpret_cast<double *>(smem + L.sc);
+  v.up = reinterpret_cast<int32_t *>(smem + L.up);
+  v.dn = reinterpret_cast<int32_t *>(smem + L.dn);
+  v.occ = reinterpret_cast<uint8_t *>(smem + L.occ);
+  v.pa = reinterpret_cast<uint8_t *>(smem + L.pa);
+  v.pb = reinterpret_cast<uint8_t *>(smem + L.pb);
+  return v;
+}
+
+// Copies instance d (n ADOs) into LDS: the state, zeroed stage buffers, the
+// neighbour tables, the parameters, the packed element map and the scalars,
+// then the damping sum of each ADO (in the tile kernel's order of modes).
+// Ends with a barrier.
+__device__ __forceinline__ void resident_load(const InstDesc &d, const ResidentView &v, int N,
+                                              int M, int n, int tid) {
+#pragma clang fp contract(off)
+  const int N2 = N * N, P = N * (N + 1) / 2;
+  const int64_t S = d.stride;
+  const double *yg = static_cast<const double *>(d.y);
+  const ParamOffsets o = param_offsets(N, M);
+  for (int q = tid; q < (N2 + 1) * n; q += kResidentThreads) {
+    const int e = q / n, i = q % n;
+    v.Y[q] = e < N2 ? yg[e * S + i] : 0.0;
+    v.A[q] = 0.0;
+    v.B[q] = 0.0;
+  }
+  for (int q = tid; q < M * n; q += kResidentThreads) {
+    const int m = q / n, i = q % n;
+    v.up[q] = d.up[m * S + i];
+    v.dn[q] = d.down[m * S + i];
+    v.occ[q] = d.occ[m * S + i];
+  }
+  for (int q = tid; q < N2; q += kResidentThreads) v.H[q] = d.params[o.h_re + q];
+  for (int q = tid; q < N; q += kResidentThreads) {
+    v.hg[q] = d.params[o.half_gamma + q];
+    v.dl[q] = d.params[o.delta + q];
+    v.tr[q] = d.params[o.trap + q];
+    v.rc[q] = d.params[o.rec + q];
+  }
+  for (int q = tid; q < M; q += kResidentThreads) {
+    v.cr[q] = d.params[o.c_re + q];
+    v.ci[q] = d.params[o.c_im + q];
+  }
+  for (int p = tid; p < P; p += kResidentThreads) {
+    v.pa[p] = static_cast<uint8_t>(elem_a(N, p));
+    v.pb[p] = static_cast<uint8_t>(elem_b(N, p));
+  }
+  for (int q = tid; q < 3 * kScalars; q += kResidentThreads)
+    v.sc[q] = q < kScalars ? d.sc_y[q] : 0.0;
+  __syncthreads();
+  for (int i = tid; i < n; i += kResidentThreads) {
+    double s = 0.0;
+    for (int m = 0; m < M; ++m)
+      s = fmad(static_cast<double>(v.occ[m * n + i]), d.params[o.nu + m], s);
+    v.damp[i] = s;
+  }
+  res_barrier();
+}
+
+// Stage buffers as in the stage launches: Y -> A -> B -> A -> Y, with the
+// scalar blocks alongside.
+struct ResidentStages {
+  double *xin[4], *xout[4];
+  int sin_[4], sout[4];
+  double coef[4];
+};
+__device__ __forceinline__ ResidentStages resident_stages(const ResidentView &v, double dt) {
+  return ResidentStages{{v.Y, v.A, v.B, v.A}, {v.A, v.B, v.A, v.Y}, {0, 1, 2, 1}, {1, 2, 1, 0},
+                        {dt / 4.0, dt / 3.0, dt / 2.0, dt}};
+}
+
+// The scalar part of stage st, on one whole wave: scalar_update_wave's
+// operations with the sink rates from LDS.
+__device__ __forceinline__ void resident_scalars(const ResidentView &v, const ResidentStages &g,
+                                                 int st, int N, int n, int lane) {
+#pragma clang fp contract(off)
+  const double *x = g.xin[st];
+  double ft = 0.0, fr = 0.0;
+  for (int q = lane; q < N; q += 64) {
+    const double pop = x[q * n];
+    ft = fmad(v.tr[q], pop, ft);
+    fr = fmad(v.rc[q], pop, fr);
+  }
+  ft = wave_sum(ft);
+  fr = wave_sum(fr);
+  if (lane == 0) {
+    const double *xs = v.sc + g.sin_[st] * kScalars;
+    double *outs = v.sc + g.sout[st] * kScalars;
+    const double xq = xs[0];
+    const double y_t = v.sc[0], y_r = v.sc[1], y_q = v.sc[2];
+    outs[0] = fmad(g.coef[st], ft, y_t);
+    outs[1] = fmad(g.coef[st], fr, y_r);
+    outs[2] = fmad(g.coef[st], xq, y_q);
+  }
+}
+
+// sigma_0 and the sink scalars of the state into history slot `slot`.
+__device__ __forceinline__ void resident_record(const InstDesc &d, const ResidentView &v, int N,
+                                                int n, int slot, int tid) {
+  const int N2 = N * N;
+  double *h = d.hist + static_cast<int64_t>(slot) * (N2 + kScalars);
+  for (int e = tid; e < N2; e += kResidentThreads) h[e] = v.Y[e * n];
+  if (tid < 3) h[N2 + tid] = v.sc[tid];
+}
+
+// The state and its scalars back to the workspace.
+__device__ __forceinline__ void resident_store(const InstDesc &d, const ResidentView &v, int N,
+                                               int n, int tid) {
+  const int64_t S = d.stride;
+  double *yo = static_cast<double *>(d.y);
+  for (int q = tid; q < N * N * n; q += kResidentThreads) yo[(q / n) * S + q % n] = v.Y[q];
+  if (tid < 3) d.sc_y[tid] = v.sc[tid];
+}
+
 // Runs steps step0 + 1 ... step0 + n_steps of instance blockIdx.x (FP64
-// storage, real H, ADO 0 = sigma_0).  With record_every > 0, the state after
-// every step whose index is a multiple of record_every is recorded in history
-// slots slot0, slot0 + 1, ... (the host sizes the chunk so that they exist).
+// storage, real H, ADO 0 = sigma_0), N and K+1 of each instance read at run
+// time (a batch may mix them).  With record_every > 0, the state after every
+// step whose index is a multiple of record_every is recorded in history slots
+// slot0, slot0 + 1, ... (the host sizes the chunk so that they exist).
 __global__ void __launch_bounds__(kResidentThreads)
     stage_resident(const InstDesc *__restrict__ descs, int64_t step0, int64_t n_steps,
                    int64_t record_every, int slot0, double dt) {
   extern __shared__ __align__(16) char res_smem[];
   const InstDesc &d = descs[blockIdx.x];
-  const int N = d.N, M = d.M, N2 = N * N, P = N * (N + 1) / 2;
+  const int N = d.N, M = d.M, P = N * (N + 1) / 2;
   const int n = static_cast<int>(d.n_ados);
-  const int64_t S = d.stride;
-  const ResidentLds L = resident_lds(N, M, n);
-  double *Y = reinterpret_cast<double *>(res_smem + L.y);
-  double *A = reinterpret_cast<double *>(res_smem + L.a);
-  double *B = reinterpret_cast<double *>(res_smem + L.b);
-  int32_t *up = reinterpret_cast<int32_t *>(res_smem + L.up);
-  int32_t *dn = reinterpret_cast<int32_t *>(res_smem + L.dn);
-  uint8_t *occ = reinterpret_cast<uint8_t *>(res_smem + L.occ);
-  double *H = reinterpret_cast<double *>(res_smem + L.h);
-  double *hg = reinterpret_cast<double *>(res_smem + L.hg);
-  double *dl = reinterpret_cast<double *>(res_smem + L.dl);
-  double *tr = reinterpret_cast<double *>(res_smem + L.tr);
-  double *rc = reinterpret_cast<double *>(res_smem + L.rc);
-  double *cr = reinterpret_cast<double *>(res_smem + L.cr);
-  double *ci = reinterpret_cast<double *>(res_smem + L.ci);
-  double *damp = reinterpret_cast<double *>(res_smem + L.damp);
-  double *sc = reinterpret_cast<double *>(res_smem + L.sc);  // [Y, A, B][kScalars]
-  uint8_t *pa = reinterpret_cast<uint8_t *>(res_smem + L.pa);
-  uint8_t *pb = reinterpret_cast<uint8_t *>(res_smem + L.pb);
+  const ResidentView v = resident_view(res_smem, resident_lds(N, M, n));
   const int tid = threadIdx.x;
-  const int KP = d.KP;
-  double *const hist = d.hist;
-  const double *yg = static_cast<const double *>(d.y);
-  const ParamOffsets o = param_offsets(N, M);
-
-  for (int q = tid; q < (N2 + 1) * n; q += kResidentThreads) {
-    const int e = q / n, i = q % n;
-    Y[q] = e < N2 ? yg[e * S + i] : 0.0;
-    A[q] = 0.0;
-    B[q] = 0.0;
-  }
-  for (int q = tid; q < M * n; q += kResidentThreads) {
-    const int m = q / n, i = q % n;
-    up[q] = d.up[m * S + i];
-    dn[q] = d.down[m * S + i];
-    occ[q] = d.occ[m * S + i];
-  }
-  for (int q = tid; q < N2; q += kResidentThreads) H[q] = d.params[o.h_re + q];
-  for (int q = tid; q < N; q += kResidentThreads) {
-    hg[q] = d.params[o.half_gamma + q];
-    dl[q] = d.params[o.delta + q];
-    tr[q] = d.params[o.trap + q];
-    rc[q] = d.params[o.rec + q];
-  }
-  for (int q = tid; q < M; q += kResidentThreads) {
-    cr[q] = d.params[o.c_re + q];
-    ci[q] = d.params[o.c_im + q];
-  }
-  for (int p = tid; p < P; p += kResidentThreads) {
-    pa[p] = static_cast<uint8_t>(elem_a(N, p));
-    pb[p] = static_cast<uint8_t>(elem_b(N, p));
-  }
-  for (int q = tid; q < 3 * kScalars; q += kResidentThreads) sc[q] = q < kScalars ? d.sc_y[q] : 0.0;
-  __syncthreads();
-  // The damping sum of each ADO, in the tile kernel's order of modes.
-  for (int i = tid; i < n; i += kResidentThreads) {
-    double s = 0.0;
-    for (int m = 0; m < M; ++m)
-      s = fmad(static_cast<double>(occ[m * n + i]), d.params[o.nu + m], s);
-    damp[i] = s;
-  }
-  res_barrier();
-
-  const double coef[4] = {dt / 4.0, dt / 3.0, dt / 2.0, dt};
-  // Stage buffers as in stage_bufs: Y -> A -> B -> A -> Y.
-  double *const xin[4] = {Y, A, B, A};
-  double *const xout[4] = {A, B, A, Y};
-  const int sin_[4] = {0, 1, 2, 1};
-  const int sout[4] = {1, 2, 1, 0};
+  resident_load(d, v, N, M, n, tid);
+  const ResidentStages g = resident_stages(v, dt);
   const int wave = tid >> 6, lane = tid & 63;
   int slot = slot0;
   for (int64_t s = 0; s < n_steps; ++s) {
     for (int st = 0; st < 4; ++st) {
+      // The scalars on the last wave (the element items fill the first
+      // waves first).
+      if (wave == kResidentThreads / 64 - 1) resident_scalars(v, g, st, N, n, lane);
+      const ResidentCtx c{N,    d.KP, n,    g.xin[st], v.Y,  g.xout[st], v.H, v.hg,
+                          v.dl, v.cr, v.ci, v.damp,    v.up, v.dn,       v.occ};
+      for (int q = tid; q < P * n; q += kResidentThreads) {
+        const int p = q / n, i = q % n;
+        resident_element(c, v.pa[p], v.pb[p], i, g.coef[st]);
+      }
+      res_barrier();
+    }
+    if (record_every > 0 && (step0 + s + 1) % record_every == 0)
+      resident_record(d, v, N, n, slot++, tid);
+  }
+  resident_store(d, v, N, n, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time N and K+1.  LDS holds the state Y and the stage buffers A and
+// B as [n][N][N] complex entries, (re, im) double pairs, with the lower
+// triangle stored as the conjugate of the upper one and the imaginary part
+// of the diagonal zero, each ADO's matrix padded to an odd number of 16-byte
+// entries (consecutive ADOs start in different banks).  Then the scalar
+// blocks of Y, A and B.
+//
+// Thread t takes packed element (a, b), p = t / W, of the ADOs j, j + W, ...,
+// j + (R - 1) W (j = t mod W, W = ceil(n / R)).  Row a and column b of a
+// matrix sit at compile-time offsets from one base address each, so the
+// commutator's operands are 16-byte loads with immediate offsets; the row of
+// H, the column of H and each item's neighbour offsets, coupling factors and
+// damping are read once per launch into registers.  A stage is then only
+// LDS loads and the element's fused multiply-adds, in tile_finish's order;
+// the stored conjugate is the exact negation that tile_finish applies to an
+// imaginary part below the diagonal, so the results equal the stage
+// launches' bitwise.
+// ---------------------------------------------------------------------------
+
+// Bytes of one ADO's matrix in the compile-time kernel's LDS.
+__host__ __device__ constexpr int fixed_ado_bytes(int N) {
+  return (N * N + (N % 2 == 0 ? 1 : 0)) * 16;
+}
+__host__ __device__ inline int fixed_lds_bytes(int N, int n) {
+  return 3 * n * fixed_ado_bytes(N) + 3 * kScalars * 8;
+}
+
+struct Cplx {
+  double re, im;
+};
+__device__ __forceinline__ Cplx lds_c(const char *base, uint32_t off) {
+  return *reinterpret_cast<const Cplx *>(base + off);
+}
+__device__ __forceinline__ void lds_put(char *base, uint32_t off, double re, double im) {
+  *reinterpret_cast<Cplx *>(base + off) = Cplx{re, im};
+}
+
+// One item's launch-invariant operands (LDS byte offsets within a buffer).
+// A missing neighbour points at the item's own entry, weighted by zero.
+template <int KP>
+struct FixedItem {
+  uint32_t own;                 // entry (a, b) of the item's ADO
+  uint32_t row, col;            // entry (a, 0) and entry (0, b) of the ADO
+  double dec;                   // damping of the element
+  uint32_t ua[KP], ub[KP];      // entry (a, b) of the deeper neighbours
+  uint32_t da[KP], db[KP];      // entry (a, b) of the shallower neighbours
+  double fa[KP], fb[KP];        // 1 where the deeper neighbour exists, else 0
+  double car[KP], cai[KP], cbr[KP], cbi[KP];  // n_m c_m of the modes of sites a and b
+};
+
+template <int N, int KP, int R>
+__global__ void __launch_bounds__(kResidentThreads)
+    stage_resident_fixed(const InstDesc *__restrict__ descs, int64_t step0, int64_t n_steps,
+                         int64_t record_every, int slot0, double dt) {
+#pragma clang fp contract(off)
+  constexpr int N2 = N * N, P = N * (N + 1) / 2, M = N * KP;
+  constexpr uint32_t SD = fixed_ado_bytes(N);
+  extern __shared__ __align__(16) char res_smem[];
+  const InstDesc &d = descs[blockIdx.x];
+  const int n = static_cast<int>(d.n_ados);
+  const int64_t S = d.stride;
+  const ParamOffsets o = param_offsets(N, M);
+  const double *const prm = d.params;
+  char *const buf0 = res_smem;
+  char *const buf1 = res_smem + n * SD;
+  char *const buf2 = res_smem + 2 * n * SD;
+  double *const sc = reinterpret_cast<double *>(res_smem + 3 * n * SD);  // [Y, A, B][kScalars]
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+
+  // The state into buffer 0, as full matrices; the stage buffers zeroed.
+  const double *yg = static_cast<const double *>(d.y);
+  for (int q = tid; q < P * n; q += kResidentThreads) {
+    const int pp = q / n, i = q % n;
+    const int a = elem_a(N, pp), b = elem_b(N, pp);
+    char *X = buf0 + i * SD;
+    if (a == b) {
+      lds_put(X, (a * N + a) * 16, yg[a * S + i], 0.0);
+    } else {
+      const int e = N + 2 * (pp - N);
+      const double re = yg[e * S + i], im = yg[(e + 1) * S + i];
+      lds_put(X, (a * N + b) * 16, re, im);
+      lds_put(X, (b * N + a) * 16, re, -im);
+    }
+  }
+  for (int q = tid; q < 2 * n * static_cast<int>(SD / 8); q += kResidentThreads)
+    reinterpret_cast<double *>(buf1)[q] = 0.0;
+  for (int q = tid; q < 3 * kScalars; q += kResidentThreads)
+    sc[q] = q < kScalars ? d.sc_y[q] : 0.0;
+  // Sink rates of site `lane` for the scalar wave.
+  const double tr_l = lane < N ? prm[o.trap + lane] : 0.0;
+  const double rc_l = lane < N ? prm[o.rec + lane] : 0.0;
+
+  // This thread's element and items.
+  const int W = (n + R - 1) / R;
+  const bool active = tid < P * W;
+  const int p = active ? tid / W : 0;
+  const int j = active ? tid - p * W : 0;
+  const int a = elem_a(N, p), b = elem_b(N, p);
+  const bool offd = a != b;
+  double hak[N], hkb[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    hak[k] = prm[o.h_re + a * N + k];
+    hkb[k] = prm[o.h_re + k * N + b];
+  }
+  const uint32_t e_own = static_cast<uint32_t>(a * N + b) * 16u;
+  const uint32_t e_conj = static_cast<uint32_t>(b * N + a) * 16u;
+  FixedItem<KP> it[R];
+  bool valid[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = j + r * W;
+    valid[r] = active && i < n;
+    const int ii = valid[r] ? i : 0;
+    FixedItem<KP> &u = it[r];
+    const uint32_t base = static_cast<uint32_t>(ii) * SD;
+    u.own = base + e_own;
+    u.row = base + static_cast<uint32_t>(a * N) * 16u;
+    u.col = base + static_cast<uint32_t>(b) * 16u;
+    double damp = 0.0;
+    for (int m = 0; m < M; ++m)
+      damp = fmad(static_cast<double>(d.occ[m * S + ii]), prm[o.nu + m], damp);
+    double dec = damp + prm[o.half_gamma + a] + prm[o.half_gamma + b];
+    if (offd) dec += prm[o.delta + a] + prm[o.delta + b];
+    u.dec = dec;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int ma = a * KP + k, mb = b * KP + k;
+      const int ja = d.up[ma * S + ii], jb = d.up[mb * S + ii];
+      u.ua[k] = static_cast<uint32_t>(ja >= 0 ? ja : ii) * SD + e_own;
+      u.ub[k] = static_cast<uint32_t>(jb >= 0 ? jb : ii) * SD + e_own;
+      u.fa[k] = ja >= 0 ? 1.0 : 0.0;
+      u.fb[k] = jb >= 0 ? 1.0 : 0.0;
+      const int za = d.down[ma * S + ii], zb = d.down[mb * S + ii];
+      u.da[k] = static_cast<uint32_t>(za >= 0 ? za : ii) * SD + e_own;
+      u.db[k] = static_cast<uint32_t>(zb >= 0 ? zb : ii) * SD + e_own;
+      const double na = static_cast<double>(d.occ[ma * S + ii]);
+      const double nb = static_cast<double>(d.occ[mb * S + ii]);
+      u.car[k] = na * prm[o.c_re + ma];
+      u.cai[k] = na * prm[o.c_im + ma];
+      u.cbr[k] = nb * prm[o.c_re + mb];
+      u.cbi[k] = nb * prm[o.c_im + mb];
+    }
+  }
+  res_barrier();
+
+  // Stage buffers as in the stage launches: Y -> A -> B -> A -> Y.
+  const double coefs[4] = {dt / 4.0, dt / 3.0, dt / 2.0, dt};
+  int slot = slot0;
+  for (int64_t s = 0; s < n_steps; ++s) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const char *const xb = st == 0 ? buf0 : (st == 2 ? buf2 : buf1);
+      char *const ob = st == 3 ? buf0 : (st == 1 ? buf2 : buf1);
+      const int sin_ = st == 0 ? 0 : (st == 2 ? 2 : 1);
+      const int sout = st == 3 ? 0 : (st == 1 ? 2 : 1);
+      const double coef = coefs[st];
       if (wave == kResidentThreads / 64 - 1) {
-        // scalar_update_wave's operations, with the sink rates from LDS, on
-        // the last wave (the element items fill the first waves first).
-        const double *x = xin[st];
+        // The scalar part (scalar_update_wave's operations).
         double ft = 0.0, fr = 0.0;
-        for (int q = lane; q < N; q += 64) {
-          const double pop = x[q * n];
-          ft = fmad(tr[q], pop, ft);
-          fr = fmad(rc[q], pop, fr);
+        if (lane < N) {
+          const double pop = lds_c(xb, static_cast<uint32_t>(lane * N + lane) * 16u).re;
+          ft = fmad(tr_l, pop, ft);
+          fr = fmad(rc_l, pop, fr);
         }
         ft = wave_sum(ft);
         fr = wave_sum(fr);
         if (lane == 0) {
-          const double *xs = sc + sin_[st] * kScalars;
-          double *outs = sc + sout[st] * kScalars;
-          const double xq = xs[0];
+          const double xq = sc[sin_ * kScalars];
           const double y_t = sc[0], y_r = sc[1], y_q = sc[2];
-          outs[0] = fmad(coef[st], ft, y_t);
-          outs[1] = fmad(coef[st], fr, y_r);
-          outs[2] = fmad(coef[st], xq, y_q);
+          sc[sout * kScalars + 0] = fmad(coef, ft, y_t);
+          sc[sout * kScalars + 1] = fmad(coef, fr, y_r);
+          sc[sout * kScalars + 2] = fmad(coef, xq, y_q);
         }
       }
-      const ResidentCtx c{N, KP, n, xin[st], Y, xout[st], H, hg, dl, cr, ci, damp, up, dn, occ};
-      for (int q = tid; q < P * n; q += kResidentThreads) {
-        const int p = q / n, i = q % n;
-        resident_element(c, pa[p], pb[p], i, coef[st]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!valid[r]) continue;
+        const FixedItem<KP> &u = it[r];
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const Cplx xkb = lds_c(xb, u.col + k * N * 16);  // X_kb
+          const Cplx xak = lds_c(xb, u.row + k * 16);      // X_ak
+          sr = fmad(-xak.re, hkb[k], fmad(hak[k], xkb.re, sr));
+          si = fmad(-xak.im, hkb[k], fmad(hak[k], xkb.im, si));
+        }
+        double ar = si, ai = -sr;
+        const Cplx x = lds_c(xb, u.own);
+        ar = fmad(-u.dec, x.re, ar);
+        ai = fmad(-u.dec, x.im, ai);
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          if (offd) {
+            const Cplx ya = lds_c(xb, u.ua[k]), yb = lds_c(xb, u.ub[k]);
+            ar = fmad(-u.fa[k], ya.im, fmad(u.fb[k], yb.im, ar));
+            ai = fmad(-u.fb[k], yb.re, fmad(u.fa[k], ya.re, ai));
+          }
+          const Cplx za = lds_c(xb, u.da[k]), zb = lds_c(xb, u.db[k]);
+          // On the diagonal the stored imaginary parts are zero.
+          ar = fmad(-u.car[k], za.im, fmad(-u.cai[k], za.re, ar));
+          ai = fmad(-u.cai[k], za.im, fmad(u.car[k], za.re, ai));
+          ar = fmad(-u.cbi[k], zb.re, fmad(u.cbr[k], zb.im, ar));
+          ai = fmad(-u.cbi[k], zb.im, fmad(-u.cbr[k], zb.re, ai));
+        }
+        const Cplx y = lds_c(buf0, u.own);
+        const double nr = fmad(coef, ar, y.re);
+        if (offd) {
+          const double ni = fmad(coef, ai, y.im);
+          lds_put(ob, u.own, nr, ni);
+          lds_put(ob, u.own - e_own + e_conj, nr, -ni);
+        } else {
+          lds_put(ob, u.own, nr, 0.0);
+        }
       }
       res_barrier();
     }
     if (record_every > 0 && (step0 + s + 1) % record_every == 0) {
-      double *h = hist + static_cast<int64_t>(slot) * (N2 + kScalars);
-      for (int e = tid; e < N2; e += kResidentThreads) h[e] = Y[e * n];
+      // sigma_0 (packed) and the sink scalars into the history ring.
+      double *h = d.hist + static_cast<int64_t>(slot) * (N2 + kScalars);
+      for (int e = tid; e < N2; e += kResidentThreads) {
+        double v;
+        if (e < N) {
+          v = lds_c(buf0, static_cast<uint32_t>(e * N + e) * 16u).re;
+        } else {
+          const int pp = N + (e - N) / 2;
+          const Cplx c = lds_c(buf0, static_cast<uint32_t>(elem_a(N, pp) * N + elem_b(N, pp)) * 16u);
+          v = (e - N) % 2 == 0 ? c.re : c.im;
+        }
+        h[e] = v;
+      }
       if (tid < 3) h[N2 + tid] = sc[tid];
       ++slot;
     }
   }
+  // The state and its scalars back to the workspace.
   double *yo = static_cast<double *>(d.y);
-  for (int q = tid; q < N2 * n; q += kResidentThreads) yo[(q / n) * S + q % n] = Y[q];
+  for (int q = tid; q < N2 * n; q += kResidentThreads) {
+    const int e = q / n, i = q % n;
+    const char *X = buf0 + i * SD;
+    double v;
+    if (e < N) {
+      v = lds_c(X, static_cast<uint32_t>(e * N + e) * 16u).re;
+    } else {
+      const int pp = N + (e - N) / 2;
+      const Cplx c = lds_c(X, static_cast<uint32_t>(elem_a(N, pp) * N + elem_b(N, pp)) * 16u);
+      v = (e - N) % 2 == 0 ? c.re : c.im;
+    }
+    yo[e * S + i] = v;
+  }
   if (tid < 3) d.sc_y[tid] = sc[tid];
 }
 

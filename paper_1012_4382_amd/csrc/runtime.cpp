@@ -39,11 +39,12 @@ hipError_t launch_init(bool mixed, const InstDesc *descs, const WorkItem *work, 
 hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int slot,
                            hipStream_t stream);
 hipError_t static_scratch(int device, void **ptr);
-int resident_lds_bytes(int N, int M, int64_t n_ados);
-hipError_t prepare_resident(int bytes);
-hipError_t launch_resident(const InstDesc *descs, int n_inst, int64_t step0, int64_t n_steps,
-                           int64_t record_every, int slot0, double dt, int lds_bytes,
-                           hipStream_t stream);
+int resident_lds_bytes(int N, int M, int64_t n_ados, bool fixed);
+bool resident_fixed_usable(int N, int KP, int R);
+hipError_t prepare_resident(int N, int KP, int R, int bytes);
+hipError_t launch_resident(int N, int KP, int R, const InstDesc *descs, int n_inst,
+                           int64_t step0, int64_t n_steps, int64_t record_every, int slot0,
+                           double dt, int lds_bytes, hipStream_t stream);
 hipError_t launch_halo(bool mixed, const InstDesc *descs, const HaloEntry *list, int n,
                        int stage, hipStream_t stream);
 
@@ -402,34 +403,65 @@ constexpr int kShapeFlagMask = 0xf00;
 // steps (a launch of a long run is cut into chunks of this many steps).
 constexpr int kResidentMaxLds = 160 * 1024;
 constexpr int64_t kResidentChunkSteps = 4096;
-// Where one workgroup runs a stage faster than a stage launch: at most one
-// packed element of one ADO per thread, and few sites (the resident kernel
-// takes N at run time, so its per-element chain grows with N; measured: the
-// dimer 2.3x faster, 7 sites at depth 2 0.86x).
+// Where one workgroup runs a stage faster than a stage launch.  The
+// compile-time kernel (every instance of the call with the same N <= 8 and
+// K+1 <= 2) holds each thread's element operands in registers and takes R
+// items (packed element x ADO) per thread, R = 2 only where that instance
+// needs no scratch memory; measured 2.3-6.8x faster than stage launches from
+// the dimer to 8 sites, two items per thread included.  The run-time-N
+// kernel, for calls that mix hierarchies, takes one item per thread and few
+// sites (its per-element chain grows with N: the dimer 2.3x faster, 7 sites
+// at depth 2 0.86x).
 constexpr int64_t kResidentMaxItems = 1024;
 constexpr int kResidentMaxSites = 4;
+constexpr int kResidentFixedSites = 8;
+constexpr int kResidentMaxR = 2;
 
-// LDS bytes of the resident kernel for the instances of a call, or 0 when the
-// call does not fit it: FP64 storage, hierarchies the LDS-tiled kernels run
-// (real H), unscaled and unfiltered, no split, small enough, and no flag that
-// asks for another kernel.
-int resident_bytes(heom_hierarchy *const *hs, int n, bool mixed, int flags, bool split) {
-  if (mixed || split || n < 1) return 0;
-  if (flags & (HEOM_NO_RESIDENT | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)) return 0;
-  if (forced_shape(flags) >= 0) return 0;
+// The resident kernel of a call: its LDS bytes (0: the call does not fit a
+// resident kernel) and which one, R = 0 for the run-time-N kernel, else the
+// compile-time instance for (N, KP) with R items per thread.
+struct ResidentPlan {
   int bytes = 0;
+  int N = 0, KP = 0, R = 0;
+};
+
+// FP64 storage, hierarchies the LDS-tiled kernels run (real H), unscaled and
+// unfiltered, no split, small enough, and no flag that asks for another
+// kernel.  A call whose instances share N and K+1 takes the compile-time
+// kernel, with the fewest items per thread that cover its largest instance.
+ResidentPlan resident_plan(heom_hierarchy *const *hs, int n, bool mixed, int flags, bool split) {
+  const ResidentPlan none;
+  if (mixed || split || n < 1) return none;
+  if (flags & (HEOM_NO_RESIDENT | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)) return none;
+  if (forced_shape(flags) >= 0) return none;
+  int bytes_rt = 0, bytes_fx = 0, R = 1;
+  bool same = true, small = true;
   for (int k = 0; k < n; ++k) {
     const heom_hierarchy *h = hs[k];
     // The LDS-tiled kernels' domain (real H, N and K+1 they are built for):
     // there the two paths agree bitwise.
-    if (!h->h_real || h->scaled || h->filter_tol > 0.0 || !has_tiled(h, false)) return 0;
+    if (!h->h_real || h->scaled || h->filter_tol > 0.0 || !has_tiled(h, false)) return none;
     const int64_t P = static_cast<int64_t>(h->N) * (h->N + 1) / 2;
-    if (h->N > kResidentMaxSites || h->n_ados * P > kResidentMaxItems) return 0;
-    const int b = resident_lds_bytes(h->N, h->M, h->n_ados);
-    if (b > kResidentMaxLds) return 0;
-    bytes = std::max(bytes, b);
+    if (h->n_ados > (1 << 20)) return none;
+    bytes_rt = std::max(bytes_rt, resident_lds_bytes(h->N, h->M, h->n_ados, false));
+    bytes_fx = std::max(bytes_fx, resident_lds_bytes(h->N, h->M, h->n_ados, true));
+    same = same && h->N == hs[0]->N && h->KP == hs[0]->KP;
+    small = small && h->N <= kResidentMaxSites && h->n_ados * P <= kResidentMaxItems;
+    int r = 1;
+    while (r <= kResidentMaxR && P * ((h->n_ados + r - 1) / r) > kResidentMaxItems) ++r;
+    R = std::max(R, r);
   }
-  return bytes;
+  ResidentPlan plan;
+  if (same && hs[0]->N <= kResidentFixedSites && hs[0]->KP <= 2 && R <= kResidentMaxR &&
+      bytes_fx <= kResidentMaxLds && resident_fixed_usable(hs[0]->N, hs[0]->KP, R)) {
+    plan.bytes = bytes_fx;
+    plan.N = hs[0]->N;
+    plan.KP = hs[0]->KP;
+    plan.R = R;
+    return plan;
+  }
+  if (small && bytes_rt <= kResidentMaxLds) plan.bytes = bytes_rt;
+  return plan;
 }
 
 // Where the device data of one call live: each instance's regions (offsets
@@ -779,9 +811,9 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
   const double coef[4] = {dt_fs / 4.0, dt_fs / 3.0, dt_fs / 2.0, dt_fs};
   // Small hierarchies: every step of a chunk in one launch of the resident
   // kernel, one workgroup per instance, records written in place.
-  const int res_bytes = resident_bytes(hs, n, mixed, flags, opt.n_halo > 0 || opt.shard);
-  if (res_bytes > 0) {
-    HEOM_HIP(prepare_resident(res_bytes), "resident kernel attributes");
+  const ResidentPlan res = resident_plan(hs, n, mixed, flags, opt.n_halo > 0 || opt.shard);
+  if (res.bytes > 0) {
+    HEOM_HIP(prepare_resident(res.N, res.KP, res.R, res.bytes), "resident kernel attributes");
     int64_t step = 0;
     while (step < n_steps) {
       int64_t run = std::min(n_steps - step, kResidentChunkSteps);
@@ -790,8 +822,9 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
         const int64_t room = kRingRecords - slot;
         run = std::min(run, (step / record_every + room) * record_every - step);
       }
-      HEOM_HIP(launch_resident(d_descs, n, step, run, want_rho ? record_every : 0,
-                               static_cast<int>(slot), dt_fs, res_bytes, stream),
+      HEOM_HIP(launch_resident(res.N, res.KP, res.R, d_descs, n, step, run,
+                               want_rho ? record_every : 0, static_cast<int>(slot), dt_fs,
+                               res.bytes, stream),
                "resident kernel");
       if (want_rho) slot += static_cast<int>((step + run) / record_every - step / record_every);
       step += run;

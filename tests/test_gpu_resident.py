@@ -1,14 +1,20 @@
-"""GPU: the resident kernel (whole RK4 steps of small hierarchies in one
+"""GPU: the resident kernels (whole RK4 steps of small hierarchies in one
 workgroup) against the stage-per-launch path and the FP64 oracle.
 
-The resident kernel repeats the tile kernel's operations in its order, so the
-two paths must agree bitwise: records, sinks and the full final state.  The
-default ("auto") takes the resident kernel where a run fits it (N <= 4, at most
-1024 packed elements x ADOs); "tiled" forces the stage kernels.  Cases: the
-dimer (15 ADOs), a 3-site hierarchy with sinks and a Matsubara term (84 ADOs),
-a 4-site depth-3 hierarchy (35 ADOs), a batch of such instances, ring drains
-over 512 records, runs longer than one resident launch, resume, and the
-efficiency entry point.
+The resident kernels repeat the tile kernel's operations in its order, so the
+paths must agree bitwise: records, sinks and the full final state.  The
+default ("auto") takes a resident kernel where a run fits one: the
+compile-time kernel where every instance of the call has the same N <= 8 and
+K+1 <= 2 (one or two packed elements x ADOs per thread, full matrices in
+LDS), else the run-time-N kernel for batches that mix hierarchies (N <= 4, at
+most 1024 elements x ADOs each); "tiled" forces the stage kernels.  Cases:
+the dimer (15 ADOs), a 3-site hierarchy with sinks and a Matsubara term (84
+ADOs), a 4-site depth-3 hierarchy (35 ADOs), the 7-site FMO model at depth 2
+(36 ADOs), an 8-site depth-1 hierarchy, two items per thread (a 6-site
+depth-3 hierarchy, 84 ADOs, and the dimer at depth 25, 351 ADOs, an odd count
+that leaves the last thread of each element one item), mixed and same-N
+batches, ring drains over 512 records, runs longer than one resident launch,
+resume, and the efficiency entry point.
 """
 import sys
 import time
@@ -60,10 +66,21 @@ def _three_site_matsubara():
     return sys_, 3, workloads.site_state(3, 1)
 
 
+def _n_site(N, depth, seed=0, K=0):
+    rng = np.random.default_rng(200 + seed)
+    H = workloads.fmo_like_hamiltonian(rng, N=N)
+    tr, rc = workloads.fmo_sinks(N=N, trap_site=N)
+    return workloads.system(H, K=K, trap=tr, rec=rc), depth, workloads.site_state(N, 1)
+
+
 CASES = {
     "dimer": lambda: (workloads.dimer()["system"], 4, workloads.dimer()["rho0"]),
     "4site_depth3": _four_site,
     "3site_K1_depth3": _three_site_matsubara,
+    "fmo_table1_depth2": lambda: (workloads.fmo_table1(), 2, workloads.site_state(7, 1)),
+    "8site_depth1": lambda: _n_site(8, 1),
+    "6site_depth3_two_items": lambda: _n_site(6, 3, seed=1),
+    "dimer_depth25_ragged": lambda: (workloads.dimer()["system"], 25, workloads.dimer()["rho0"]),
 }
 
 
@@ -95,8 +112,9 @@ def test_resident_equals_tiled_and_oracle(name):
 
 
 def test_resident_batch_ring_drains_and_chunks():
-    """A batch of small instances (one workgroup each), 1100 records (two
-    ring drains), and a run without records longer than one resident launch."""
+    """A batch that mixes hierarchies (the run-time-N kernel, one workgroup
+    per instance), 1100 records (two ring drains), and a run without records
+    longer than one resident launch."""
     batch = [CASES["dimer"](), _four_site(1), _four_site(2), _three_site_matsubara()]
     hs = [heom.Hierarchy(s, d) for s, d, _ in batch]
     r0 = [r for _, _, r in batch]
@@ -110,6 +128,29 @@ def test_resident_batch_ring_drains_and_chunks():
     _say("case: resident batch, 9000 steps without records (three resident launches)")
     _, s1, _ = heom.propagate_batch(hs, r0, 1.0, 9000, want_rho=False)
     _, s2, _ = heom.propagate_batch(hs, r0, 1.0, 9000, want_rho=False, kernel="tiled")
+    assert np.array_equal(np.asarray(s1), np.asarray(s2))
+    for h in hs:
+        h.close()
+
+
+def test_resident_fixed_batch_ring_drains_and_chunks():
+    """A batch of 4-site instances of depths 3 and 5 (the compile-time kernel
+    with two items per thread, which the smaller instance takes too), 1100
+    records and a run longer than one resident launch."""
+    batch = [_four_site(4, depth=3), _four_site(5, depth=5), _four_site(6, depth=3)]
+    hs = [heom.Hierarchy(s, d) for s, d, _ in batch]
+    r0 = [r for _, _, r in batch]
+    _say("case: compile-time resident batch, 4 sites depths 3/5/3, 1100 steps, every step")
+    rho, sinks, _ = heom.propagate_batch(hs, r0, 1.0, 1100, record_every=1)
+    rho_t, sinks_t, _ = heom.propagate_batch(hs, r0, 1.0, 1100, record_every=1, kernel="tiled")
+    for k in range(len(hs)):
+        assert np.array_equal(rho[k], rho_t[k]), k
+    assert np.array_equal(np.asarray(sinks), np.asarray(sinks_t))
+    ref = oracle.propagate(batch[1][0], 5, r0[1], 1.0, 1100, record_every=100)
+    assert _rel(rho[1][::100], ref["rho"]) <= FP64_TOL
+    _say("case: compile-time resident batch, 9000 steps without records")
+    _, s1, ws1 = heom.propagate_batch(hs, r0, 1.0, 9000, want_rho=False)
+    _, s2, ws2 = heom.propagate_batch(hs, r0, 1.0, 9000, want_rho=False, kernel="tiled")
     assert np.array_equal(np.asarray(s1), np.asarray(s2))
     for h in hs:
         h.close()
