@@ -26,13 +26,22 @@ constexpr int64_t kRingRecords = 512;
 // ADOs are padded to a multiple of this in every plane (one wave of lanes).
 constexpr int64_t kPlanePad = 64;
 
-// Layout of one ADO ("packed Hermitian", N*N reals): plane e < N holds the
+// Layout of one ADO ("packed Hermitian", N*N reals): element e < N is the
 // real diagonal entry (e, e); for each pair a < b in row-major order, with pair
-// index p, plane N + 2p holds Re sigma_ab and plane N + 2p + 1 holds Im sigma_ab.
-// Element e of ADO i lives at plane[e * stride + i] (structure of arrays), so
-// lanes that handle consecutive ADOs read consecutive addresses.
+// index p, element N + 2p is Re sigma_ab and element N + 2p + 1 is Im sigma_ab.
+// In device memory each element has a plane of `stride` values (structure of
+// arrays, so lanes that handle consecutive ADOs read consecutive addresses):
+// diagonal element e of ADO i lives at e * stride + i, and the two planes of
+// pair p form one block of (Re, Im) pairs, ADO i at (N + 2p) * stride + 2i and
+// + 1, so one 16-byte access (8 in FP32 storage) moves both parts.
 HEOM_HD inline int pair_index(int N, int a, int b) {  // a < b
   return a * N - a * (a + 1) / 2 + (b - a - 1);
+}
+// Index of packed element e of ADO i in planes of stride S.
+HEOM_HD inline int64_t elem_index(int N, int e, int64_t S, int64_t i) {
+  if (e < N) return e * S + i;
+  const int q = (e - N) & 1;
+  return (e - q) * S + 2 * i + q;
 }
 
 // Per-instance parameters, all converted to rad/fs (energies) and 1/fs

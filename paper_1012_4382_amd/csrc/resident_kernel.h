@@ -183,7 +183,7 @@ __device__ __forceinline__ void resident_load(const InstDesc &d, const ResidentV
   const ParamOffsets o = param_offsets(N, M);
   for (int q = tid; q < (N2 + 1) * n; q += kResidentThreads) {
     const int e = q / n, i = q % n;
-    v.Y[q] = e < N2 ? yg[e * S + i] : 0.0;
+    v.Y[q] = e < N2 ? yg[elem_index(N, e, S, i)] : 0.0;
     v.A[q] = 0.0;
     v.B[q] = 0.0;
   }
@@ -271,7 +271,7 @@ __device__ __forceinline__ void resident_store(const InstDesc &d, const Resident
                                                int n, int tid) {
   const int64_t S = d.stride;
   double *yo = static_cast<double *>(d.y);
-  for (int q = tid; q < N * N * n; q += kResidentThreads) yo[(q / n) * S + q % n] = v.Y[q];
+  for (int q = tid; q < N * N * n; q += kResidentThreads) yo[elem_index(N, q / n, S, q % n)] = v.Y[q];
   if (tid < 3) d.sc_y[tid] = v.sc[tid];
 }
 
@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(kResidentThreads)
       lds_put(X, (a * N + a) * 16, yg[a * S + i], 0.0);
     } else {
       const int e = N + 2 * (pp - N);
-      const double re = yg[e * S + i], im = yg[(e + 1) * S + i];
+      const double re = yg[e * S + 2 * i], im = yg[e * S + 2 * i + 1];
       lds_put(X, (a * N + b) * 16, re, im);
       lds_put(X, (b * N + a) * 16, re, -im);
     }
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(kResidentThreads)
       const Cplx c = lds_c(X, static_cast<uint32_t>(elem_a(N, pp) * N + elem_b(N, pp)) * 16u);
       v = (e - N) % 2 == 0 ? c.re : c.im;
     }
-    yo[e * S + i] = v;
+    yo[elem_index(N, e, S, i)] = v;
   }
   if (tid < 3) d.sc_y[tid] = sc[tid];
 }

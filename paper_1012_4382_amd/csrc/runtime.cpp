@@ -1420,7 +1420,7 @@ int heom_read_state(const heom_hierarchy *h, int precision, const void *d_worksp
   std::vector<double> packed(N2);
   for (int64_t i = 0; i < h->n_ados; ++i) {
     for (size_t e = 0; e < N2; ++e) {
-      const size_t idx = e * static_cast<size_t>(h->stride) + i;
+      const size_t idx = static_cast<size_t>(elem_index(N, static_cast<int>(e), h->stride, i));
       packed[e] = (mixed && i == 0) ? y0[e] : (mixed ? p32[idx] : p64[idx]);
     }
     unpack_hermitian(N, packed.data(), state_out + 2 * N2 * i);
@@ -1581,7 +1581,8 @@ int heom_read_state_sharded(const heom_shard *s, int precision, const void *d_wo
   for (int r = 0; r < s->n_ranks; ++r) {
     const heom_hierarchy *g = s->rank[r];
     for (int64_t li = 0; li < g->n_ados; ++li) {
-      for (size_t e = 0; e < N2; ++e) packed[e] = planes[r][e * g->stride + li];
+      for (size_t e = 0; e < N2; ++e)
+        packed[e] = planes[r][elem_index(N, static_cast<int>(e), g->stride, li)];
       unpack_hermitian(N, packed.data(), state_out + 2 * N2 * (s->first[r] + li));
     }
   }

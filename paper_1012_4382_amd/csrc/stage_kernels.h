@@ -106,6 +106,25 @@ __device__ __forceinline__ void st_off(HEOM_GLOBAL T *base, uint32_t off, T v) {
   else
     *p = v;
 }
+// (Re, Im) of a pair element of one ADO: one access of two values (16 bytes
+// in FP64 storage, 8 in FP32) at byte offset `off` of the pair's block.
+template <typename T>
+using Pair2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ Pair2<T> ld_pair(const HEOM_GLOBAL T *block, uint32_t off) {
+  return *(const HEOM_GLOBAL Pair2<T> *)((const HEOM_GLOBAL char *)block + off);
+}
+template <bool STREAM, typename T>
+__device__ __forceinline__ void st_pair(HEOM_GLOBAL T *block, uint32_t off, T re, T im) {
+  HEOM_GLOBAL Pair2<T> *p = (HEOM_GLOBAL Pair2<T> *)((HEOM_GLOBAL char *)block + off);
+  Pair2<T> v;
+  v.x = re;
+  v.y = im;
+  if constexpr (STREAM)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 // Buffers used by stage s.
 struct StageBufs {
@@ -249,7 +268,7 @@ __device__ __forceinline__ void update_fixed(const InstDesc &d, int64_t i, int s
     if constexpr (MIXED && IS0)
       x[e] = bufs.x0[e];
     else
-      x[e] = static_cast<C>(X[e * S + i]);
+      x[e] = static_cast<C>(X[elem_index(N, e, S, i)]);
   }
   // Neighbour indices and occupations.
   int32_t up[M], dn[M];
@@ -301,15 +320,15 @@ __device__ __forceinline__ void update_fixed(const InstDesc &d, int64_t i, int s
         for (int k = 0; k < KP; ++k) {
           const int ja = up[a * KP + k];
           if (ja >= 0) {
-            const C vr = static_cast<C>(X[e * S + ja]);
-            const C vi = static_cast<C>(X[(e + 1) * S + ja]);
+            const C vr = static_cast<C>(X[elem_index(N, e, S, ja)]);
+            const C vi = static_cast<C>(X[elem_index(N, e + 1, S, ja)]);
             ar -= vi;
             ai += vr;
           }
           const int jb = up[b * KP + k];
           if (jb >= 0) {
-            const C vr = static_cast<C>(X[e * S + jb]);
-            const C vi = static_cast<C>(X[(e + 1) * S + jb]);
+            const C vr = static_cast<C>(X[elem_index(N, e, S, jb)]);
+            const C vi = static_cast<C>(X[elem_index(N, e + 1, S, jb)]);
             ar += vi;
             ai -= vr;
           }
@@ -322,8 +341,8 @@ __device__ __forceinline__ void update_fixed(const InstDesc &d, int64_t i, int s
         const int mb = b * KP + k;
         const int ja = dn[ma];
         if (ja >= 0) {
-          const C vr = static_cast<C>(X[e * S + ja]);
-          const C vi = (a == b) ? C(0) : static_cast<C>(X[(e + 1) * S + ja]);
+          const C vr = static_cast<C>(X[elem_index(N, e, S, ja)]);
+          const C vi = (a == b) ? C(0) : static_cast<C>(X[elem_index(N, e + 1, S, ja)]);
           const C cr = occ[ma] * static_cast<C>(P[o.c_re + ma]);
           const C ci = occ[ma] * static_cast<C>(P[o.c_im + ma]);
           // i (cr + i ci)(vr + i vi) = -(ci vr + cr vi) + i (cr vr - ci vi)
@@ -332,8 +351,8 @@ __device__ __forceinline__ void update_fixed(const InstDesc &d, int64_t i, int s
         }
         const int jb = dn[mb];
         if (jb >= 0) {
-          const C vr = static_cast<C>(X[e * S + jb]);
-          const C vi = (a == b) ? C(0) : static_cast<C>(X[(e + 1) * S + jb]);
+          const C vr = static_cast<C>(X[elem_index(N, e, S, jb)]);
+          const C vi = (a == b) ? C(0) : static_cast<C>(X[elem_index(N, e + 1, S, jb)]);
           const C cr = occ[mb] * static_cast<C>(P[o.c_re + mb]);
           const C ci = occ[mb] * static_cast<C>(P[o.c_im + mb]);
           // -i (cr - i ci)(vr + i vi) = -(ci vr - cr vi) ... expanded:
@@ -352,21 +371,21 @@ __device__ __forceinline__ void update_fixed(const InstDesc &d, int64_t i, int s
         yr = bufs.y0[e];
         yi = (a == b) ? C(0) : bufs.y0[e + 1];
       } else {
-        yr = static_cast<C>(Yp[e * S + i]);
-        yi = (a == b) ? C(0) : static_cast<C>(Yp[(e + 1) * S + i]);
+        yr = static_cast<C>(Yp[elem_index(N, e, S, i)]);
+        yi = (a == b) ? C(0) : static_cast<C>(Yp[elem_index(N, e + 1, S, i)]);
       }
       const C nr = yr + coef * ar;
       const C ni = yi + coef * ai;
       if constexpr (MIXED && IS0) {
         bufs.out0[e] = nr;
-        Out[e * S + i] = static_cast<T>(nr);
+        Out[elem_index(N, e, S, i)] = static_cast<T>(nr);
         if (a != b) {
           bufs.out0[e + 1] = ni;
-          Out[(e + 1) * S + i] = static_cast<T>(ni);
+          Out[elem_index(N, e + 1, S, i)] = static_cast<T>(ni);
         }
       } else {
-        Out[e * S + i] = static_cast<T>(nr);
-        if (a != b) Out[(e + 1) * S + i] = static_cast<T>(ni);
+        Out[elem_index(N, e, S, i)] = static_cast<T>(nr);
+        if (a != b) Out[elem_index(N, e + 1, S, i)] = static_cast<T>(ni);
       }
       if constexpr (IS0) {
         if (stage == 3 && hist_slot >= 0) {
@@ -431,7 +450,7 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
 
   auto ld = [&](int e) -> C {  // own stage input, packed element e
     if constexpr (MIXED && IS0) return x0[e];
-    return static_cast<C>(X[e * S + i]);
+    return static_cast<C>(X[elem_index(N, e, S, i)]);
   };
   auto elem = [&](int c, int b) -> Cx<C> {
     if (c == b) return {ld(c), C(0)};
@@ -473,20 +492,20 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
         if (a != b) {
           const int ja = up[ma * S + i];
           if (ja >= 0) {
-            ar -= static_cast<C>(X[(e + 1) * S + ja]);
-            ai += static_cast<C>(X[e * S + ja]);
+            ar -= static_cast<C>(X[elem_index(N, e + 1, S, ja)]);
+            ai += static_cast<C>(X[elem_index(N, e, S, ja)]);
           }
           const int jb = up[mb * S + i];
           if (jb >= 0) {
-            ar += static_cast<C>(X[(e + 1) * S + jb]);
-            ai -= static_cast<C>(X[e * S + jb]);
+            ar += static_cast<C>(X[elem_index(N, e + 1, S, jb)]);
+            ai -= static_cast<C>(X[elem_index(N, e, S, jb)]);
           }
         }
         const int ja = down[ma * S + i];
         if (ja >= 0) {
           const C n = static_cast<C>(occ[ma * S + i]);
-          const C vr = static_cast<C>(X[e * S + ja]);
-          const C vi = (a == b) ? C(0) : static_cast<C>(X[(e + 1) * S + ja]);
+          const C vr = static_cast<C>(X[elem_index(N, e, S, ja)]);
+          const C vi = (a == b) ? C(0) : static_cast<C>(X[elem_index(N, e + 1, S, ja)]);
           const C cr = n * static_cast<C>(P[o.c_re + ma]);
           const C ci = n * static_cast<C>(P[o.c_im + ma]);
           ar -= ci * vr + cr * vi;
@@ -495,8 +514,8 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
         const int jb = down[mb * S + i];
         if (jb >= 0) {
           const C n = static_cast<C>(occ[mb * S + i]);
-          const C vr = static_cast<C>(X[e * S + jb]);
-          const C vi = (a == b) ? C(0) : static_cast<C>(X[(e + 1) * S + jb]);
+          const C vr = static_cast<C>(X[elem_index(N, e, S, jb)]);
+          const C vi = (a == b) ? C(0) : static_cast<C>(X[elem_index(N, e + 1, S, jb)]);
           const C cr = n * static_cast<C>(P[o.c_re + mb]);
           const C ci = n * static_cast<C>(P[o.c_im + mb]);
           ar += cr * vi - ci * vr;
@@ -511,8 +530,8 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
         yr = bufs.y0[e];
         yi = (a == b) ? C(0) : bufs.y0[e + 1];
       } else {
-        yr = static_cast<C>(Yp[e * S + i]);
-        yi = (a == b) ? C(0) : static_cast<C>(Yp[(e + 1) * S + i]);
+        yr = static_cast<C>(Yp[elem_index(N, e, S, i)]);
+        yi = (a == b) ? C(0) : static_cast<C>(Yp[elem_index(N, e + 1, S, i)]);
       }
       const C nr = yr + coef * ar;
       const C ni = yi + coef * ai;
@@ -522,8 +541,8 @@ __device__ __forceinline__ void update_generic(const InstDesc &d, int64_t i, int
         out0[e] = nr;
         if (a != b) out0[e + 1] = ni;
       }
-      Out[e * S + i] = static_cast<T>(nr);
-      if (a != b) Out[(e + 1) * S + i] = static_cast<T>(ni);
+      Out[elem_index(N, e, S, i)] = static_cast<T>(nr);
+      if (a != b) Out[elem_index(N, e + 1, S, i)] = static_cast<T>(ni);
       if constexpr (IS0) {
         if (stage == 3 && hist_slot >= 0) {
           double *h = d.hist + static_cast<int64_t>(hist_slot) * (N2 + kScalars);
@@ -712,8 +731,10 @@ template <int N, int KP, int A, int B, typename C, typename T, bool SCALED>
 __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> &L) {
   constexpr int E = ent_re(N, A, B);
   const int lane = c.lane;
-  const HEOM_GLOBAL T *pre = c.X + E * c.S;         // wave-uniform plane bases
-  const HEOM_GLOBAL T *pim = c.X + (E + 1) * c.S;
+  // Wave-uniform base: the diagonal element's plane, or the pair's block of
+  // (Re, Im) pairs (each neighbour one access of both parts).
+  const HEOM_GLOBAL T *pre = c.X + E * c.S;
+  constexpr uint32_t W = (A != B ? 2 : 1) * sizeof(T);  // bytes per ADO in that plane
   const uint32_t self = static_cast<uint32_t>(c.i);
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
@@ -722,27 +743,36 @@ __device__ __forceinline__ void tile_load(const TileCtx<T> &c, ElemLoads<C, KP> 
     if constexpr (A != B) {
       const int ja = c.sup[ma * kTile + lane];
       const int jb = c.sup[mb * kTile + lane];
-      const uint32_t oa = (ja >= 0 ? static_cast<uint32_t>(ja) : self) * sizeof(T);
-      const uint32_t ob = (jb >= 0 ? static_cast<uint32_t>(jb) : self) * sizeof(T);
-      L.yar[k] = static_cast<C>(ld_off(pre, oa));
-      L.yai[k] = static_cast<C>(ld_off(pim, oa));
-      L.ybr[k] = static_cast<C>(ld_off(pre, ob));
-      L.ybi[k] = static_cast<C>(ld_off(pim, ob));
+      const uint32_t oa = (ja >= 0 ? static_cast<uint32_t>(ja) : self) * W;
+      const uint32_t ob = (jb >= 0 ? static_cast<uint32_t>(jb) : self) * W;
+      const Pair2<T> ya = ld_pair(pre, oa), yb = ld_pair(pre, ob);
+      L.yar[k] = static_cast<C>(ya.x);
+      L.yai[k] = static_cast<C>(ya.y);
+      L.ybr[k] = static_cast<C>(yb.x);
+      L.ybi[k] = static_cast<C>(yb.y);
     }
     const int ja = c.sdn[ma * kTile + lane];
     const int jb = c.sdn[mb * kTile + lane];
-    const uint32_t oa = (ja >= 0 ? static_cast<uint32_t>(ja) : self) * sizeof(T);
-    const uint32_t ob = (jb >= 0 ? static_cast<uint32_t>(jb) : self) * sizeof(T);
-    L.zar[k] = static_cast<C>(ld_off(pre, oa));
-    L.zbr[k] = static_cast<C>(ld_off(pre, ob));
+    const uint32_t oa = (ja >= 0 ? static_cast<uint32_t>(ja) : self) * W;
+    const uint32_t ob = (jb >= 0 ? static_cast<uint32_t>(jb) : self) * W;
     if constexpr (A != B) {
-      L.zai[k] = static_cast<C>(ld_off(pim, oa));
-      L.zbi[k] = static_cast<C>(ld_off(pim, ob));
+      const Pair2<T> za = ld_pair(pre, oa), zb = ld_pair(pre, ob);
+      L.zar[k] = static_cast<C>(za.x);
+      L.zai[k] = static_cast<C>(za.y);
+      L.zbr[k] = static_cast<C>(zb.x);
+      L.zbi[k] = static_cast<C>(zb.y);
+    } else {
+      L.zar[k] = static_cast<C>(ld_off(pre, oa));
+      L.zbr[k] = static_cast<C>(ld_off(pre, ob));
     }
   }
-  const uint32_t oi = self * sizeof(T);
-  L.str = static_cast<C>(ld_off(c.Yp + E * c.S, oi));
-  if constexpr (A != B) L.sti = static_cast<C>(ld_off(c.Yp + (E + 1) * c.S, oi));
+  if constexpr (A != B) {
+    const Pair2<T> st = ld_pair(c.Yp + E * c.S, self * W);
+    L.str = static_cast<C>(st.x);
+    L.sti = static_cast<C>(st.y);
+  } else {
+    L.str = static_cast<C>(ld_off(c.Yp + E * c.S, self * W));
+  }
   if constexpr (SCALED) {
     // Weights of the couplings along the modes of sites A and B, by the
     // ADO's occupation of each mode (loaded with the gathers).
@@ -832,8 +862,10 @@ __device__ __forceinline__ void tile_finish(const TileCtx<T> &c, const ElemLoads
   // In FP32-mixed runs sigma_0 is written by tile_sigma0 alone.
   if (sizeof(T) == 4 && c.i == 0) return;
   const uint32_t oi = static_cast<uint32_t>(c.i) * sizeof(T);
-  st_off<STREAM>(c.Out + E * c.S, oi, static_cast<T>(nr));
-  if constexpr (A != B) st_off<STREAM>(c.Out + (E + 1) * c.S, oi, static_cast<T>(ni));
+  if constexpr (A != B)
+    st_pair<STREAM>(c.Out + E * c.S, 2 * oi, static_cast<T>(nr), static_cast<T>(ni));
+  else
+    st_off<STREAM>(c.Out + E * c.S, oi, static_cast<T>(nr));
 }
 
 // One chunk of wave G's elements (element indices OFF + K): all global loads
@@ -901,8 +933,10 @@ __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
   const int A = elem_a(N, p), B = elem_b(N, p);
   const bool off = A != B;
   const int E = ent_re(N, A, B);
+  // The element's plane (diagonal) or the pair's block, (Re, Im) of ADO j at
+  // 2j and 2j + 1.
   const HEOM_GLOBAL T *pre = c.X + E * c.S;
-  const HEOM_GLOBAL T *pim = c.X + (E + 1) * c.S;
+  const uint32_t W = off ? 2u : 1u;
   // Loads, as tile_load issues them for ADO 0 (entry 0 of the LDS tables; a
   // missing neighbour reads ADO 0 itself and is weighted by zero).
   double yar[KP], yai[KP], ybr[KP], ybi[KP], zar[KP], zai[KP], zbr[KP], zbi[KP];
@@ -912,21 +946,21 @@ __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
     yar[k] = yai[k] = ybr[k] = ybi[k] = zai[k] = zbi[k] = 0.0;
     if (off) {
       const int ja = c.sup[ma * kTile], jb = c.sup[mb * kTile];
-      const uint32_t oa = static_cast<uint32_t>(ja >= 0 ? ja : 0) * sizeof(T);
-      const uint32_t ob = static_cast<uint32_t>(jb >= 0 ? jb : 0) * sizeof(T);
-      yar[k] = ld_off(pre, oa);
-      yai[k] = ld_off(pim, oa);
-      ybr[k] = ld_off(pre, ob);
-      ybi[k] = ld_off(pim, ob);
+      const uint32_t oa = static_cast<uint32_t>(ja >= 0 ? ja : 0) * W;
+      const uint32_t ob = static_cast<uint32_t>(jb >= 0 ? jb : 0) * W;
+      yar[k] = pre[oa];
+      yai[k] = pre[oa + 1];
+      ybr[k] = pre[ob];
+      ybi[k] = pre[ob + 1];
     }
     const int ja = c.sdn[ma * kTile], jb = c.sdn[mb * kTile];
-    const uint32_t oa = static_cast<uint32_t>(ja >= 0 ? ja : 0) * sizeof(T);
-    const uint32_t ob = static_cast<uint32_t>(jb >= 0 ? jb : 0) * sizeof(T);
-    zar[k] = ld_off(pre, oa);
-    zbr[k] = ld_off(pre, ob);
+    const uint32_t oa = static_cast<uint32_t>(ja >= 0 ? ja : 0) * W;
+    const uint32_t ob = static_cast<uint32_t>(jb >= 0 ? jb : 0) * W;
+    zar[k] = pre[oa];
+    zbr[k] = pre[ob];
     if (off) {
-      zai[k] = ld_off(pim, oa);
-      zbi[k] = ld_off(pim, ob);
+      zai[k] = pre[oa + 1];
+      zbi[k] = pre[ob + 1];
     }
   }
   const double str = c.y0[E];
@@ -986,7 +1020,7 @@ __device__ __forceinline__ void tile_sigma0(const TileCtx<T> &c, int p) {
   c.Out[E * c.S] = static_cast<T>(nr);
   if (off) {
     c.out0[E + 1] = ni;
-    c.Out[(E + 1) * c.S] = static_cast<T>(ni);
+    c.Out[E * c.S + 1] = static_cast<T>(ni);  // ADO 0 of the pair's block
   }
 }
 
@@ -1067,19 +1101,30 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   }
   const int64_t i = static_cast<int64_t>(w.first) + lane;
   const bool valid = i < d.n_ados;
-  // Stage the tile: wave w loads planes w, w + W, ... (a compile-time count,
-  // clamped in bounds, so that every load is issued before the first wait).
+  // Stage the tile: wave w loads element slots w, w + W, ... (a compile-time
+  // count, clamped in bounds, so that every load is issued before the first
+  // wait): slot s < N is diagonal plane s, slot N + p pair p's block, both
+  // parts in one access.
   const int64_t ic = valid ? i : 0;  // invalid lanes load ADO 0 and store defaults
-  constexpr int RX = (N2 + W - 1) / W;
+  constexpr int NS = N * (N + 1) / 2;
+  constexpr int RX = (NS + W - 1) / W;
   constexpr int RM = (M + W - 1) / W;
-  T vx[RX];
+  T vx[RX], vy[RX];
   int32_t vu[RM], vd[RM];
   uint8_t vo[RM];
   const uint32_t ic4 = static_cast<uint32_t>(ic) * 4u;
+  const uint32_t icb = static_cast<uint32_t>(ic) * static_cast<uint32_t>(sizeof(T));
 #pragma unroll
   for (int r = 0; r < RX; ++r) {
-    const int e = min(wave + r * W, N2 - 1);
-    vx[r] = ld_off(X + e * S, static_cast<uint32_t>(ic) * static_cast<uint32_t>(sizeof(T)));
+    const int sl = min(wave + r * W, NS - 1);
+    if (sl < N) {
+      vx[r] = ld_off(X + sl * S, icb);
+      vy[r] = T(0);
+    } else {
+      const Pair2<T> v = ld_pair(X + (N + 2 * (sl - N)) * S, 2 * icb);
+      vx[r] = v.x;
+      vy[r] = v.y;
+    }
   }
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
@@ -1090,8 +1135,14 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   }
 #pragma unroll
   for (int r = 0; r < RX; ++r) {
-    const int e = wave + r * W;
-    if (e < N2) sx[e * kTile + lane] = valid ? vx[r] : T(0);
+    const int sl = wave + r * W;
+    if (sl < N) {
+      sx[sl * kTile + lane] = valid ? vx[r] : T(0);
+    } else if (sl < NS) {
+      const int e = N + 2 * (sl - N);
+      sx[e * kTile + lane] = valid ? vx[r] : T(0);
+      sx[(e + 1) * kTile + lane] = valid ? vy[r] : T(0);
+    }
   }
   if (wave == 0) sx[N2 * kTile + lane] = T(0);
 #pragma unroll
@@ -1275,12 +1326,15 @@ __device__ __forceinline__ void wide_load(const WideCtx<T> &c, int a, int b,
   const int N = c.N, t = c.t;
   const int E = wide_plane<T>(c.sent[a * N + b].re);
   const bool offd = a != b;
-  const uint32_t Ei = offd ? E + 1 : E;  // a plane that exists
   const uint32_t sz = static_cast<uint32_t>(sizeof(T));
+  // The element's plane (diagonal) or the pair's block, (Re, Im) of ADO j at
+  // 2j and 2j + 1.  On the diagonal the imaginary load reads the next value
+  // of the plane (in bounds: plane N follows the diagonal planes), unused.
+  const uint32_t W = offd ? 2 * sz : sz;
   const uint32_t pre = static_cast<uint32_t>(E) * c.S * sz;
-  const uint32_t pim = Ei * c.S * sz;
+  const uint32_t pim = pre + sz;
   const uint32_t self = static_cast<uint32_t>(c.i);
-  auto off = [&](int j) -> uint32_t { return (j >= 0 ? static_cast<uint32_t>(j) : self) * sz; };
+  auto off = [&](int j) -> uint32_t { return (j >= 0 ? static_cast<uint32_t>(j) : self) * W; };
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int ma = a * KP + k, mb = b * KP + k;
@@ -1302,8 +1356,8 @@ __device__ __forceinline__ void wide_load(const WideCtx<T> &c, int a, int b,
     L.str = static_cast<C>(c.y0[E]);
     if (offd) L.sti = static_cast<C>(c.y0[E + 1]);
   } else {
-    L.str = static_cast<C>(ld_off(c.Yp, pre + self * sz));
-    const C v = static_cast<C>(ld_off(c.Yp, pim + self * sz));
+    L.str = static_cast<C>(ld_off(c.Yp, pre + self * W));
+    const C v = static_cast<C>(ld_off(c.Yp, pim + self * W));
     if (offd) L.sti = v;
   }
 }
@@ -1396,9 +1450,10 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
     if (offd) c.out0[E + 1] = ni;
   }
   const uint32_t sz = static_cast<uint32_t>(sizeof(T));
-  const uint32_t oi = static_cast<uint32_t>(c.i) * sz;
-  st_off<false>(c.Out, static_cast<uint32_t>(E) * c.S * sz + oi, static_cast<T>(nr));
-  if (offd) st_off<false>(c.Out, static_cast<uint32_t>(E + 1) * c.S * sz + oi, static_cast<T>(ni));
+  const uint32_t base = static_cast<uint32_t>(E) * c.S * sz;
+  const uint32_t oi = static_cast<uint32_t>(c.i) * (offd ? 2 * sz : sz);
+  st_off<false>(c.Out, base + oi, static_cast<T>(nr));
+  if (offd) st_off<false>(c.Out, base + oi + sz, static_cast<T>(ni));
 }
 
 template <typename T, int KP, bool SCALED>
@@ -1441,7 +1496,7 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   for (int idx = tid; idx < N2 * kWideAdos; idx += blockDim.x) {
     const int e = idx / kWideAdos, t = idx % kWideAdos;
     const int64_t i = static_cast<int64_t>(w.first) + t;
-    const T v = X[e * S + (i < d.n_ados ? i : 0)];
+    const T v = X[elem_index(N, e, S, i < d.n_ados ? i : 0)];
     sx[idx] = i < d.n_ados ? v : T(0);
   }
   if (tid < kWideAdos) sx[N2 * kWideAdos + tid] = T(0);
@@ -1571,7 +1626,8 @@ __global__ void __launch_bounds__(256) init_state(const InstDesc *__restrict__ d
   const ParamOffsets o = param_offsets(d.N, d.M);
   T *y = static_cast<T *>(d.y);
   const bool s0 = i == 0 && !(d.flags & kInstNoSigma0);
-  for (int e = 0; e < N2; ++e) y[e * d.stride + i] = s0 ? static_cast<T>(d.params[o.rho0 + e]) : T(0);
+  for (int e = 0; e < N2; ++e)
+    y[elem_index(d.N, e, d.stride, i)] = s0 ? static_cast<T>(d.params[o.rho0 + e]) : T(0);
   if (s0) {
     if (sizeof(T) == 4)
       for (int e = 0; e < N2; ++e) d.y0[e] = d.params[o.rho0 + e];
@@ -1595,7 +1651,9 @@ __global__ void __launch_bounds__(256) halo_fill(const InstDesc *__restrict__ de
   const T *src = static_cast<const T *>(stage_bufs(ds, stage).x);
   T *dst = static_cast<T *>(const_cast<void *>(stage_bufs(dd, stage).x));
   const int N = dd.N;
-  auto copy = [&](int e) { dst[e * dd.stride + h.dst_index] = src[e * ds.stride + h.src_index]; };
+  auto copy = [&](int e) {
+    dst[elem_index(dd.N, e, dd.stride, h.dst_index)] = src[elem_index(ds.N, e, ds.stride, h.src_index)];
+  };
   for (int a = 0; a < N; ++a) {
     const bool in_a = (h.sites >> a) & 1;
     if (in_a) copy(a);
@@ -1621,9 +1679,10 @@ __global__ void __launch_bounds__(64) filter_ados(const InstDesc *__restrict__ d
   T *y = static_cast<T *>(d.y);
   const int N2 = d.N * d.N;
   double mx = 0.0;
-  for (int e = 0; e < N2; ++e) mx = fmax(mx, fabs(static_cast<double>(y[e * d.stride + i])));
+  for (int e = 0; e < N2; ++e)
+    mx = fmax(mx, fabs(static_cast<double>(y[elem_index(d.N, e, d.stride, i)])));
   if (mx < d.filter_tol)
-    for (int e = 0; e < N2; ++e) y[e * d.stride + i] = T(0);
+    for (int e = 0; e < N2; ++e) y[elem_index(d.N, e, d.stride, i)] = T(0);
 }
 
 // Writes the current sigma_0 and scalars of each instance to history slot.
@@ -1636,7 +1695,7 @@ __global__ void snapshot(const InstDesc *__restrict__ descs, int n_inst, int slo
   double *h = d.hist + static_cast<int64_t>(slot) * (N2 + kScalars);
   const T *y = static_cast<const T *>(d.y);
   for (int e = threadIdx.x; e < N2; e += blockDim.x)
-    h[e] = (sizeof(T) == 4) ? d.y0[e] : static_cast<double>(y[e * d.stride]);
+    h[e] = (sizeof(T) == 4) ? d.y0[e] : static_cast<double>(y[elem_index(d.N, e, d.stride, 0)]);
   if (threadIdx.x < 3) h[N2 + threadIdx.x] = d.sc_y[threadIdx.x];
 }
 
