@@ -106,6 +106,9 @@ struct InstDesc {
   int32_t N, M, KP, flags;
   int32_t levels, pad_;  // scaled: occupations 0 .. levels - 1 in the weight tables
   double filter_tol;     // > 0: ADOs below it are zeroed after every step
+  // The neighbour tables as 16-bit offsets from the ADO's own index (0: no
+  // neighbour), [M][stride], or null where an offset does not fit.
+  const int16_t *up16, *down16;
 };
 
 // One halo ADO of a split hierarchy: before each stage, ADO src_index of
@@ -167,6 +170,7 @@ struct heom_hierarchy {
     int device = -1;
     int32_t *up = nullptr, *down = nullptr;
     uint8_t *occ = nullptr;
+    int16_t *up16 = nullptr, *down16 = nullptr;  // null where an offset does not fit
   };
   mutable std::mutex mu;
   mutable std::vector<DeviceTables> dev;

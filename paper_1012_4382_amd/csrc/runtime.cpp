@@ -153,6 +153,29 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
   return L;
 }
 
+// h's neighbour tables as offsets from each ADO's own index (0 where there is
+// no neighbour: no ADO is its own neighbour), or false where an offset does
+// not fit 16 bits.
+bool tables16(const heom_hierarchy *h, std::vector<int16_t> *u16, std::vector<int16_t> *d16) {
+  const size_t n = h->up.size();
+  const int64_t S = h->stride;
+  if (S <= 0) return false;
+  u16->assign(n, 0);
+  d16->assign(n, 0);
+  for (size_t q = 0; q < n; ++q) {
+    const int64_t i = static_cast<int64_t>(q % static_cast<size_t>(S));
+    const int32_t ju = h->up[q], jd = h->down[q];
+    for (int side = 0; side < 2; ++side) {
+      const int32_t j = side ? jd : ju;
+      if (j < 0) continue;
+      const int64_t delta = j - i;
+      if (delta == 0 || delta < -32767 || delta > 32767) return false;
+      (side ? *d16 : *u16)[q] = static_cast<int16_t>(delta);
+    }
+  }
+  return true;
+}
+
 // The device copy of h's neighbour tables on `device`, uploaded on first use
 // (with upload = false a missing copy is an error: nothing is allocated).
 int ensure_device_tables(const heom_hierarchy *h, int device, heom_hierarchy::DeviceTables *out,
@@ -190,6 +213,23 @@ int ensure_device_tables(const heom_hierarchy *h, int device, heom_hierarchy::De
     (void)hipFree(t.down);
     (void)hipFree(t.occ);
     return dev_fail(e, "hipMemcpy(tables)");
+  }
+  // The 16-bit form, where every neighbour lies within 32767 ADOs: the stage
+  // kernels stage it instead, 4 bytes per mode and ADO instead of 8.
+  std::vector<int16_t> u16, d16;
+  if (tables16(h, &u16, &d16)) {
+    const size_t n16 = u16.size() * sizeof(int16_t);
+    bool ok = hipMalloc(reinterpret_cast<void **>(&t.up16), n16) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void **>(&t.down16), n16) == hipSuccess;
+    ok = ok && hipMemcpy(t.up16, u16.data(), n16, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(t.down16, d16.data(), n16, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+      // An optional copy: without it the kernels stage the 32-bit tables.
+      (void)hipGetLastError();
+      if (t.up16) (void)hipFree(t.up16);
+      if (t.down16) (void)hipFree(t.down16);
+      t.up16 = t.down16 = nullptr;
+    }
   }
   h->dev.push_back(t);
   *out = t;
@@ -595,6 +635,8 @@ int run_impl(heom_hierarchy *const *hs, int n, int precision, int flags, const i
     d.up = t.up;
     d.down = t.down;
     d.occ = t.occ;
+    d.up16 = t.up16;
+    d.down16 = t.down16;
     d.n_ados = hs[k]->n_ados;
     d.stride = hs[k]->stride;
     d.N = hs[k]->N;
@@ -1645,6 +1687,8 @@ void heom_destroy(heom_hierarchy *h) {
     (void)hipFree(t.up);
     (void)hipFree(t.down);
     (void)hipFree(t.occ);
+    if (t.up16) (void)hipFree(t.up16);
+    if (t.down16) (void)hipFree(t.down16);
   }
   delete h;
 }

@@ -114,6 +114,21 @@ template <typename T>
 __device__ __forceinline__ Pair2<T> ld_pair(const HEOM_GLOBAL T *block, uint32_t off) {
   return *(const HEOM_GLOBAL Pair2<T> *)((const HEOM_GLOBAL char *)block + off);
 }
+// Neighbour index of ADO i along one mode from a table row that is either
+// int32 indices (t16 false) or int16 offsets from i (0: no neighbour), read
+// with one aligned 32-bit load in both cases (the 16-bit form as the word that
+// holds ADOs 2k and 2k + 1, so adjacent lanes share it), no branch: the
+// element size and the decoding are wave-uniform selects.  -1: no neighbour.
+__device__ __forceinline__ int table_load(const HEOM_GLOBAL char *row, bool t16, uint32_t i) {
+  const uint32_t off = t16 ? (i & ~1u) * 2u : i * 4u;
+  return *(const HEOM_GLOBAL int32_t *)(row + off);
+}
+__device__ __forceinline__ int table_decode(int32_t w, bool t16, uint32_t i) {
+  if (!t16) return w;
+  const int32_t delta = (i & 1u) ? (w >> 16) : ((w << 16) >> 16);
+  return delta != 0 ? static_cast<int>(i) + delta : -1;
+}
+
 template <bool STREAM, typename T>
 __device__ __forceinline__ void st_pair(HEOM_GLOBAL T *block, uint32_t off, T re, T im) {
   HEOM_GLOBAL Pair2<T> *p = (HEOM_GLOBAL Pair2<T> *)((HEOM_GLOBAL char *)block + off);
@@ -1126,12 +1141,21 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
       vy[r] = v.y;
     }
   }
+  // Neighbour tables: the 16-bit offsets where the instance has them (half
+  // the bytes), else the 32-bit indices, through the same loads.
+  const bool t16 = d.up16 != nullptr;
+  const HEOM_GLOBAL char *upb = (const HEOM_GLOBAL char *)(
+      t16 ? reinterpret_cast<const char *>(d.up16) : reinterpret_cast<const char *>(d.up));
+  const HEOM_GLOBAL char *dnb = (const HEOM_GLOBAL char *)(
+      t16 ? reinterpret_cast<const char *>(d.down16) : reinterpret_cast<const char *>(d.down));
+  const uint32_t row_bytes = static_cast<uint32_t>(S) * (t16 ? 2u : 4u);
+  const uint32_t ic32 = static_cast<uint32_t>(ic);
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
     const int m = min(wave + r * W, M - 1);
-    vu[r] = ld_off(up + m * S, ic4);
-    vd[r] = ld_off(dn + m * S, ic4);
-    vo[r] = ld_off(oc + m * S, static_cast<uint32_t>(ic));
+    vu[r] = table_load(upb + m * row_bytes, t16, ic32);
+    vd[r] = table_load(dnb + m * row_bytes, t16, ic32);
+    vo[r] = ld_off(oc + m * S, ic32);
   }
 #pragma unroll
   for (int r = 0; r < RX; ++r) {
@@ -1149,8 +1173,12 @@ __global__ void __launch_bounds__(64 * tile_waves(N, sizeof(T) == 8, SHAPE),
   for (int r = 0; r < RM; ++r) {
     const int m = wave + r * W;
     if (m < M) {
-      sup[m * kTile + lane] = valid ? vu[r] : -1;
-      sdn[m * kTile + lane] = valid ? vd[r] : -1;
+      // Valid lanes decode at their own index (invalid ones store -1).
+      const uint32_t iself = static_cast<uint32_t>(w.first) + static_cast<uint32_t>(lane);
+      const int ju = table_decode(vu[r], t16, iself);
+      const int jd = table_decode(vd[r], t16, iself);
+      sup[m * kTile + lane] = valid ? ju : -1;
+      sdn[m * kTile + lane] = valid ? jd : -1;
       socc[m * kTile + lane] = valid ? vo[r] : 0;
     }
   }
@@ -1316,10 +1344,13 @@ __device__ __forceinline__ int wide_plane(uint32_t off) {
 }
 
 // Phase 1 of element (a, b) of the lane's ADO (tile_load with runtime a, b):
-// every global load, at 32-bit byte offsets from the buffers' bases.  On the
-// diagonal the loads that the tile kernel skips read the element's own real
-// plane instead; their values are not used.  X0SRC reads sigma_0's state
-// from its FP64 copy.
+// every global load, at 32-bit byte offsets from the buffers' bases.  An
+// off-diagonal element reads each neighbour's (Re, Im) with one access from
+// the pair's block; a diagonal one reads the real plane and skips the loads
+// the tile kernel skips (their values are not used).  The element list puts
+// the N diagonal elements first and a wave takes kWideSlots consecutive ones
+// per pass, so for N a multiple of kWideSlots the branch is wave-uniform.
+// X0SRC reads sigma_0's state from its FP64 copy.
 template <typename C, typename T, bool X0SRC, int KP>
 __device__ __forceinline__ void wide_load(const WideCtx<T> &c, int a, int b,
                                           WideLoads<C, KP> &L) {
@@ -1327,38 +1358,56 @@ __device__ __forceinline__ void wide_load(const WideCtx<T> &c, int a, int b,
   const int E = wide_plane<T>(c.sent[a * N + b].re);
   const bool offd = a != b;
   const uint32_t sz = static_cast<uint32_t>(sizeof(T));
-  // The element's plane (diagonal) or the pair's block, (Re, Im) of ADO j at
-  // 2j and 2j + 1.  On the diagonal the imaginary load reads the next value
-  // of the plane (in bounds: plane N follows the diagonal planes), unused.
-  const uint32_t W = offd ? 2 * sz : sz;
   const uint32_t pre = static_cast<uint32_t>(E) * c.S * sz;
-  const uint32_t pim = pre + sz;
   const uint32_t self = static_cast<uint32_t>(c.i);
-  auto off = [&](int j) -> uint32_t { return (j >= 0 ? static_cast<uint32_t>(j) : self) * W; };
+  if (offd) {
+    const HEOM_GLOBAL T *blk = c.X + static_cast<uint32_t>(E) * c.S;
+    auto off = [&](int j) -> uint32_t {
+      return (j >= 0 ? static_cast<uint32_t>(j) : self) * (2 * sz);
+    };
 #pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int ma = a * KP + k, mb = b * KP + k;
-    L.jua[k] = c.sup[ma * kWideAdos + t];
-    L.jub[k] = c.sup[mb * kWideAdos + t];
-    const int jda = c.sdn[ma * kWideAdos + t], jdb = c.sdn[mb * kWideAdos + t];
-    const uint32_t oa = off(L.jua[k]), ob = off(L.jub[k]), da = off(jda), db = off(jdb);
-    L.yar[k] = static_cast<C>(ld_off(c.X, pre + oa));
-    L.yai[k] = static_cast<C>(ld_off(c.X, pim + oa));
-    L.ybr[k] = static_cast<C>(ld_off(c.X, pre + ob));
-    L.ybi[k] = static_cast<C>(ld_off(c.X, pim + ob));
-    L.zar[k] = static_cast<C>(ld_off(c.X, pre + da));
-    L.zai[k] = static_cast<C>(ld_off(c.X, pim + da));
-    L.zbr[k] = static_cast<C>(ld_off(c.X, pre + db));
-    L.zbi[k] = static_cast<C>(ld_off(c.X, pim + db));
-  }
-  L.sti = C(0);
-  if constexpr (X0SRC) {
-    L.str = static_cast<C>(c.y0[E]);
-    if (offd) L.sti = static_cast<C>(c.y0[E + 1]);
+    for (int k = 0; k < KP; ++k) {
+      const int ma = a * KP + k, mb = b * KP + k;
+      L.jua[k] = c.sup[ma * kWideAdos + t];
+      L.jub[k] = c.sup[mb * kWideAdos + t];
+      const int jda = c.sdn[ma * kWideAdos + t], jdb = c.sdn[mb * kWideAdos + t];
+      const Pair2<T> ya = ld_pair(blk, off(L.jua[k])), yb = ld_pair(blk, off(L.jub[k]));
+      const Pair2<T> za = ld_pair(blk, off(jda)), zb = ld_pair(blk, off(jdb));
+      L.yar[k] = static_cast<C>(ya.x);
+      L.yai[k] = static_cast<C>(ya.y);
+      L.ybr[k] = static_cast<C>(yb.x);
+      L.ybi[k] = static_cast<C>(yb.y);
+      L.zar[k] = static_cast<C>(za.x);
+      L.zai[k] = static_cast<C>(za.y);
+      L.zbr[k] = static_cast<C>(zb.x);
+      L.zbi[k] = static_cast<C>(zb.y);
+    }
+    if constexpr (X0SRC) {
+      L.str = static_cast<C>(c.y0[E]);
+      L.sti = static_cast<C>(c.y0[E + 1]);
+    } else {
+      const Pair2<T> st = ld_pair(c.Yp + static_cast<uint32_t>(E) * c.S, self * (2 * sz));
+      L.str = static_cast<C>(st.x);
+      L.sti = static_cast<C>(st.y);
+    }
   } else {
-    L.str = static_cast<C>(ld_off(c.Yp, pre + self * W));
-    const C v = static_cast<C>(ld_off(c.Yp, pim + self * W));
-    if (offd) L.sti = v;
+    auto off = [&](int j) -> uint32_t { return (j >= 0 ? static_cast<uint32_t>(j) : self) * sz; };
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int ma = a * KP + k, mb = b * KP + k;
+      L.jua[k] = c.sup[ma * kWideAdos + t];
+      L.jub[k] = c.sup[mb * kWideAdos + t];
+      const int jda = c.sdn[ma * kWideAdos + t], jdb = c.sdn[mb * kWideAdos + t];
+      L.yar[k] = L.yai[k] = L.ybr[k] = L.ybi[k] = C(0);
+      L.zar[k] = static_cast<C>(ld_off(c.X, pre + off(jda)));
+      L.zbr[k] = static_cast<C>(ld_off(c.X, pre + off(jdb)));
+      L.zai[k] = L.zbi[k] = C(0);
+    }
+    L.sti = C(0);
+    if constexpr (X0SRC)
+      L.str = static_cast<C>(c.y0[E]);
+    else
+      L.str = static_cast<C>(ld_off(c.Yp, pre + self * sz));
   }
 }
 
@@ -1451,9 +1500,11 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
   }
   const uint32_t sz = static_cast<uint32_t>(sizeof(T));
   const uint32_t base = static_cast<uint32_t>(E) * c.S * sz;
-  const uint32_t oi = static_cast<uint32_t>(c.i) * (offd ? 2 * sz : sz);
-  st_off<false>(c.Out, base + oi, static_cast<T>(nr));
-  if (offd) st_off<false>(c.Out, base + oi + sz, static_cast<T>(ni));
+  if (offd)
+    st_pair<false>(c.Out + static_cast<uint32_t>(E) * c.S, static_cast<uint32_t>(c.i) * (2 * sz),
+                   static_cast<T>(nr), static_cast<T>(ni));
+  else
+    st_off<false>(c.Out, base + static_cast<uint32_t>(c.i) * sz, static_cast<T>(nr));
 }
 
 template <typename T, int KP, bool SCALED>
@@ -1493,11 +1544,23 @@ __global__ void __launch_bounds__(64 * kWideWaves)
   // Stage the tile (invalid ADOs of the last tile read ADO 0 and store 0),
   // the entry table with H, the parameters, the neighbour tables and the
   // element map.
-  for (int idx = tid; idx < N2 * kWideAdos; idx += blockDim.x) {
-    const int e = idx / kWideAdos, t = idx % kWideAdos;
+  // Element slots: slot s < N is diagonal plane s, slot N + p pair p's block
+  // (both parts in one access).
+  const int NS = N * (N + 1) / 2;
+  for (int idx = tid; idx < NS * kWideAdos; idx += blockDim.x) {
+    const int sl = idx / kWideAdos, t = idx % kWideAdos;
     const int64_t i = static_cast<int64_t>(w.first) + t;
-    const T v = X[elem_index(N, e, S, i < d.n_ados ? i : 0)];
-    sx[idx] = i < d.n_ados ? v : T(0);
+    const bool ok = i < d.n_ados;
+    const int64_t ic = ok ? i : 0;
+    if (sl < N) {
+      const T v = X[sl * S + ic];
+      sx[sl * kWideAdos + t] = ok ? v : T(0);
+    } else {
+      const int e = N + 2 * (sl - N);
+      const Pair2<T> v = ld_pair(X + e * S, static_cast<uint32_t>(ic) * 2u * sizeof(T));
+      sx[e * kWideAdos + t] = ok ? v.x : T(0);
+      sx[(e + 1) * kWideAdos + t] = ok ? v.y : T(0);
+    }
   }
   if (tid < kWideAdos) sx[N2 * kWideAdos + tid] = T(0);
   constexpr uint32_t kPlaneBytes = kWideAdos * sizeof(T);
@@ -1521,12 +1584,21 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     sci[idx] = Pg[o.c_im + idx];
     snu[idx] = Pg[o.nu + idx];
   }
+  const bool t16 = d.up16 != nullptr;
+  const HEOM_GLOBAL char *upb = (const HEOM_GLOBAL char *)(
+      t16 ? reinterpret_cast<const char *>(d.up16) : reinterpret_cast<const char *>(d.up));
+  const HEOM_GLOBAL char *dnb = (const HEOM_GLOBAL char *)(
+      t16 ? reinterpret_cast<const char *>(d.down16) : reinterpret_cast<const char *>(d.down));
+  const uint32_t row_bytes = static_cast<uint32_t>(S) * (t16 ? 2u : 4u);
   for (int idx = tid; idx < M * kWideAdos; idx += blockDim.x) {
     const int m = idx / kWideAdos, t = idx % kWideAdos;
     const int64_t i = static_cast<int64_t>(w.first) + t;
     const bool ok = i < d.n_ados;
-    sup[idx] = ok ? gmem(d.up)[m * S + i] : -1;
-    sdn[idx] = ok ? gmem(d.down)[m * S + i] : -1;
+    const uint32_t ic = static_cast<uint32_t>(ok ? i : 0);
+    const int ju = table_decode(table_load(upb + m * row_bytes, t16, ic), t16, ic);
+    const int jd = table_decode(table_load(dnb + m * row_bytes, t16, ic), t16, ic);
+    sup[idx] = ok ? ju : -1;
+    sdn[idx] = ok ? jd : -1;
     socc[idx] = ok ? gmem(d.occ)[m * S + i] : 0;
   }
   for (int p = tid; p < P; p += blockDim.x) {

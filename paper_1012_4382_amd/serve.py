@@ -127,10 +127,12 @@ class GpuBackend:
 
 
 def tables_bytes(h) -> int:
-    """Device bytes of the neighbour tables of a hierarchy (two int32 tables and
-    the uint8 occupations, [modes][ADOs padded to 64])."""
+    """Device bytes of the neighbour tables of a hierarchy, at most: two int32
+    tables, the uint8 occupations and, where every neighbour lies within
+    32767 ADOs, the two tables again as int16 offsets ([modes][ADOs padded to
+    64])."""
     stride = (h.n_ados + 63) // 64 * 64
-    return h.n_modes * stride * 9
+    return h.n_modes * stride * 13
 
 
 class Engine:
