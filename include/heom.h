@@ -122,7 +122,9 @@ typedef struct {
  * and amplitudes from eq:gamma and its Matsubara expansion, the multi-index
  * map of every ADO with |n| <= depth, and the neighbour tables n +- e_m
  * (Appendix B: each matrix is linked to its neighbours).  Host-only work; the
- * tables are copied to a device on first use there.
+ * tables are copied to a device on first use there: 9 bytes per mode and ADO
+ * (ADOs padded to a multiple of 64), plus 4 more where every neighbour lies
+ * within 32767 ADOs (a 16-bit copy the stage kernels read instead).
  * Errors: HEOM_E_INVALID (see the field comments; also a Matsubara frequency
  * within 1e-9 relative of gamma, or more than 2^31 - 1 ADOs), HEOM_E_NOMEM.
  * On success *out owns the handle; release it with heom_destroy. */

@@ -159,7 +159,7 @@ Layout make_layout(heom_hierarchy *const *hs, int n, int precision) {
 bool tables16(const heom_hierarchy *h, std::vector<int16_t> *u16, std::vector<int16_t> *d16) {
   const size_t n = h->up.size();
   const int64_t S = h->stride;
-  if (S <= 0) return false;
+  if (S <= 0 || n == 0) return false;
   u16->assign(n, 0);
   d16->assign(n, 0);
   for (size_t q = 0; q < n; ++q) {
