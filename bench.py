@@ -416,8 +416,9 @@ def _stage_kernel_timing(heom, torch, hs, rho0s, stream, kernel, precision="fp64
 def _small(heom, torch, workloads, stream, reps=5):
     """Small hierarchies, where a stage launch lasts about its launch floor:
     the dimer (15 ADOs, 1000 steps, every step recorded), a 3-site solve with a
-    Matsubara term (84 ADOs), a 7-site depth-2 solve (36 ADOs) and a 6-site
-    depth-3 solve (84 ADOs, two packed elements x ADOs per thread), 5000 steps
+    Matsubara term (84 ADOs), a 7-site depth-2 solve (36 ADOs), a 6-site
+    depth-3 solve (84 ADOs, two packed elements x ADOs per thread) and an
+    8-site depth-2 solve (45 ADOs, four per thread on 512 threads), 5000 steps
     with records every 10, each on the default path (the resident kernel:
     every step of a chunk in one launch) and on the stage-per-launch path,
     wall clock per solve (the faster of `reps`), results compared bitwise."""
@@ -430,11 +431,16 @@ def _small(heom, torch, workloads, stream, reps=5):
     six = {"system": workloads.system(workloads.fmo_like_hamiltonian(rng, N=6), trap=tr6,
                                       rec=rc6),
            "depth": 3, "rho0": workloads.site_state(6, 1)}
+    tr8, rc8 = workloads.fmo_sinks(N=8, trap_site=8)
+    eight = {"system": workloads.system(workloads.fmo_like_hamiltonian(rng, N=8), trap=tr8,
+                                        rec=rc8),
+             "depth": 2, "rho0": workloads.site_state(8, 1)}
     cases = [("dimer_depth4_1000steps_every_step", workloads.dimer(), 1000, 1),
              ("3site_k1_depth3_5000steps", three, 5000, 10),
              ("fmo_like_7site_depth2_5000steps", workloads.fmo_like(seed=0, site=1, depth=2),
               5000, 10),
-             ("6site_depth3_5000steps", six, 5000, 10)]
+             ("6site_depth3_5000steps", six, 5000, 10),
+             ("8site_depth2_5000steps", eight, 5000, 10)]
     out = {}
     for name, w, steps, rec in cases:
         h = heom.Hierarchy(w["system"], w["depth"])

@@ -168,14 +168,18 @@ int resident_lds_bytes(int N, int M, int64_t n_ados, bool fixed) {
   return fixed ? fixed_lds_bytes(N, n) : resident_lds(N, M, n).total;
 }
 
+// Threads per workgroup of the compile-time resident kernel with R items per
+// thread: 1024 for one or two, 512 for four (the registers of four items).
+int resident_threads(int R) { return R >= 4 ? 512 : 1024; }
+
 // The resident kernel with compile-time N, K+1 and items per thread R, or
-// nullptr where not built (N <= 8, K+1 <= 2, R <= 2; more items per thread
-// spill registers at every N).
+// nullptr where not built (N <= 8, K+1 <= 2, R in {1, 2, 4}).
 template <int N, int KP>
 const void *resident_fixed_r(int R) {
   switch (R) {
-    case 1: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 1>);
-    case 2: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 2>);
+    case 1: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 1, 1024>);
+    case 2: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 2, 1024>);
+    case 4: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 4, 512>);
     default: return nullptr;
   }
 }
@@ -228,8 +232,9 @@ hipError_t launch_resident(int N, int KP, int R, const InstDesc *descs, int n_in
   const void *k = resident_kernel(N, KP, R);
   if (!k) return hipErrorInvalidValue;
   void *args[] = {&descs, &step0, &n_steps, &record_every, &slot0, &dt};
-  return hipLaunchKernel(k, dim3(n_inst), dim3(kResidentThreads), args,
-                         static_cast<size_t>(lds_bytes), stream);
+  const int threads = R == 0 ? kResidentThreads : resident_threads(R);
+  return hipLaunchKernel(k, dim3(n_inst), dim3(threads), args, static_cast<size_t>(lds_bytes),
+                         stream);
 }
 
 // `streaming` selects the tile kernel instance with non-temporal output

@@ -320,8 +320,9 @@ __global__ void __launch_bounds__(kResidentThreads)
 // entries (consecutive ADOs start in different banks).  Then the scalar
 // blocks of Y, A and B.
 //
-// Thread t takes packed element (a, b), p = t / W, of the ADOs j, j + W, ...,
-// j + (R - 1) W (j = t mod W, W = ceil(n / R)).  Row a and column b of a
+// Thread t of THREADS takes packed element (a, b), p = t / W, of the ADOs j,
+// j + W, ..., j + (R - 1) W (j = t mod W, W = ceil(n / R)); four items per
+// thread run on 512 threads, so that each has the registers for them.  Row a and column b of a
 // matrix sit at compile-time offsets from one base address each, so the
 // commutator's operands are 16-byte loads with immediate offsets; the row of
 // H, the column of H and each item's neighbour offsets, coupling factors and
@@ -363,8 +364,8 @@ struct FixedItem {
   double car[KP], cai[KP], cbr[KP], cbi[KP];  // n_m c_m of the modes of sites a and b
 };
 
-template <int N, int KP, int R>
-__global__ void __launch_bounds__(kResidentThreads)
+template <int N, int KP, int R, int THREADS>
+__global__ void __launch_bounds__(THREADS)
     stage_resident_fixed(const InstDesc *__restrict__ descs, int64_t step0, int64_t n_steps,
                          int64_t record_every, int slot0, double dt) {
 #pragma clang fp contract(off)
@@ -385,7 +386,7 @@ __global__ void __launch_bounds__(kResidentThreads)
 
   // The state into buffer 0, as full matrices; the stage buffers zeroed.
   const double *yg = static_cast<const double *>(d.y);
-  for (int q = tid; q < P * n; q += kResidentThreads) {
+  for (int q = tid; q < P * n; q += THREADS) {
     const int pp = q / n, i = q % n;
     const int a = elem_a(N, pp), b = elem_b(N, pp);
     char *X = buf0 + i * SD;
@@ -398,9 +399,9 @@ __global__ void __launch_bounds__(kResidentThreads)
       lds_put(X, (b * N + a) * 16, re, -im);
     }
   }
-  for (int q = tid; q < 2 * n * static_cast<int>(SD / 8); q += kResidentThreads)
+  for (int q = tid; q < 2 * n * static_cast<int>(SD / 8); q += THREADS)
     reinterpret_cast<double *>(buf1)[q] = 0.0;
-  for (int q = tid; q < 3 * kScalars; q += kResidentThreads)
+  for (int q = tid; q < 3 * kScalars; q += THREADS)
     sc[q] = q < kScalars ? d.sc_y[q] : 0.0;
   // Sink rates of site `lane` for the scalar wave.
   const double tr_l = lane < N ? prm[o.trap + lane] : 0.0;
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(kResidentThreads)
       const int sin_ = st == 0 ? 0 : (st == 2 ? 2 : 1);
       const int sout = st == 3 ? 0 : (st == 1 ? 2 : 1);
       const double coef = coefs[st];
-      if (wave == kResidentThreads / 64 - 1) {
+      if (wave == THREADS / 64 - 1) {
         // The scalar part (scalar_update_wave's operations).
         double ft = 0.0, fr = 0.0;
         if (lane < N) {
@@ -534,7 +535,7 @@ __global__ void __launch_bounds__(kResidentThreads)
     if (record_every > 0 && (step0 + s + 1) % record_every == 0) {
       // sigma_0 (packed) and the sink scalars into the history ring.
       double *h = d.hist + static_cast<int64_t>(slot) * (N2 + kScalars);
-      for (int e = tid; e < N2; e += kResidentThreads) {
+      for (int e = tid; e < N2; e += THREADS) {
         double v;
         if (e < N) {
           v = lds_c(buf0, static_cast<uint32_t>(e * N + e) * 16u).re;
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(kResidentThreads)
   }
   // The state and its scalars back to the workspace.
   double *yo = static_cast<double *>(d.y);
-  for (int q = tid; q < N2 * n; q += kResidentThreads) {
+  for (int q = tid; q < N2 * n; q += THREADS) {
     const int e = q / n, i = q % n;
     const char *X = buf0 + i * SD;
     double v;

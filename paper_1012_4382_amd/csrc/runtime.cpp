@@ -41,6 +41,7 @@ hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int sl
 hipError_t static_scratch(int device, void **ptr);
 int resident_lds_bytes(int N, int M, int64_t n_ados, bool fixed);
 bool resident_fixed_usable(int N, int KP, int R);
+int resident_threads(int R);
 hipError_t prepare_resident(int N, int KP, int R, int bytes);
 hipError_t launch_resident(int N, int KP, int R, const InstDesc *descs, int n_inst,
                            int64_t step0, int64_t n_steps, int64_t record_every, int slot0,
@@ -446,16 +447,17 @@ constexpr int64_t kResidentChunkSteps = 4096;
 // Where one workgroup runs a stage faster than a stage launch.  The
 // compile-time kernel (every instance of the call with the same N <= 8 and
 // K+1 <= 2) holds each thread's element operands in registers and takes R
-// items (packed element x ADO) per thread, R = 2 only where that instance
-// needs no scratch memory; measured 2.3-6.8x faster than stage launches from
-// the dimer to 8 sites, two items per thread included.  The run-time-N
+// items (packed element x ADO) per thread: one or two on 1024 threads (two
+// only where that instance needs no scratch memory), else four on 512;
+// measured 1.6-6x faster than stage launches from the dimer to 8 sites at
+// depth 2.  The run-time-N
 // kernel, for calls that mix hierarchies, takes one item per thread and few
 // sites (its per-element chain grows with N: the dimer 2.3x faster, 7 sites
 // at depth 2 0.86x).
 constexpr int64_t kResidentMaxItems = 1024;
 constexpr int kResidentMaxSites = 4;
 constexpr int kResidentFixedSites = 8;
-constexpr int kResidentMaxR = 2;
+constexpr int kResidentMaxR = 4;
 
 // The resident kernel of a call: its LDS bytes (0: the call does not fit a
 // resident kernel) and which one, R = 0 for the run-time-N kernel, else the
@@ -488,8 +490,19 @@ ResidentPlan resident_plan(heom_hierarchy *const *hs, int n, bool mixed, int fla
     same = same && h->N == hs[0]->N && h->KP == hs[0]->KP;
     small = small && h->N <= kResidentMaxSites && h->n_ados * P <= kResidentMaxItems;
     int r = 1;
-    while (r <= kResidentMaxR && P * ((h->n_ados + r - 1) / r) > kResidentMaxItems) ++r;
+    while (r <= 2 && P * ((h->n_ados + r - 1) / r) > kResidentMaxItems) ++r;
     R = std::max(R, r);
+  }
+  // Two items per thread where that instance keeps them in registers, else
+  // four on half the threads (the same number of items).
+  if (R == 2 && hs[0]->N <= kResidentFixedSites && hs[0]->KP <= 2 &&
+      !resident_fixed_usable(hs[0]->N, hs[0]->KP, 2))
+    R = 4;
+  if (R == 4) {
+    for (int k = 0; k < n; ++k) {
+      const int64_t P = static_cast<int64_t>(hs[k]->N) * (hs[k]->N + 1) / 2;
+      if (P * ((hs[k]->n_ados + 3) / 4) > resident_threads(4)) R = kResidentMaxR + 1;
+    }
   }
   ResidentPlan plan;
   if (same && hs[0]->N <= kResidentFixedSites && hs[0]->KP <= 2 && R <= kResidentMaxR &&
