@@ -179,8 +179,9 @@ def test_resident_resume_and_efficiency():
 
 def test_resident_is_faster_for_the_dimer():
     """The point of the resident kernel: the dimer's steps in a few launches
-    instead of four stage launches each (measured 2.0x over 10000 steps,
-    workspace and stream reused, the best of three calls)."""
+    instead of four stage launches each (the compile-time form measured 5.6x
+    over 5000 steps with records every 10, the run-time form 2.0x; here 10000
+    steps, workspace and stream reused, the best of three calls, bar 1.5x)."""
     import torch
 
     w = workloads.dimer()
