@@ -1272,11 +1272,28 @@ constexpr int kWideMaxKP = 4;  // modes per site (K + 1) the wide kernel is buil
 // Entry (r, c) of a packed ADO in the wide kernel's LDS tile: byte offsets
 // of its real and imaginary planes (the zero plane N*N for the imaginary part
 // of a diagonal entry; bit 31 of `im` set when the imaginary part is
-// negated, r > c), and H_rc.  One 16-byte read gives the commutator both.
+// negated, r > c), and H_rc in the storage precision: FP64, or with FP32
+// storage the FP32 value (rounded once, as a conversion at each use would
+// round it) in the low word of `h`.  One 16-byte read gives the commutator
+// both.
 struct WideEntry {
   uint32_t re, im;
   double h;
 };
+template <typename T>
+__device__ __forceinline__ double wide_h_slot(double h) {
+  if constexpr (sizeof(T) == 4)
+    return __longlong_as_double(static_cast<long long>(__float_as_uint(static_cast<float>(h))));
+  else
+    return h;
+}
+template <typename T>
+__device__ __forceinline__ T wide_h_value(double slot) {
+  if constexpr (sizeof(T) == 4)
+    return __uint_as_float(static_cast<uint32_t>(__double_as_longlong(slot)));
+  else
+    return slot;
+}
 
 // LDS layout of the wide kernel (byte offsets; every region 16-byte aligned).
 // `levels` > 0 (scaled hierarchies) adds the coupling-weight tables.
@@ -1319,6 +1336,7 @@ struct WideCtx {
   const HEOM_GLOBAL T *X, *Yp;
   HEOM_GLOBAL T *Out;
   const double *sx0;  // LDS copy of the FP64 sigma_0 stage input (FP32 storage)
+  const HEOM_GLOBAL double *hg;  // H_re (FP64, parameter block): the FP64 sigma_0 pass
   const HEOM_GLOBAL double *y0;
   HEOM_GLOBAL double *out0;
   uint32_t S;  // plane stride in ADOs; every buffer of a wide launch is below 4 GiB
@@ -1432,9 +1450,24 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
       return static_cast<C>(*reinterpret_cast<const T *>(sxt + off));
     }
   };
+  // The entry's sign bit moved onto the value (negation, exact).
   auto xim = [&](uint32_t im) -> C {
     const C v = xre(im & 0x7fffffffu);
-    return (im >> 31) ? -v : v;
+    if constexpr (sizeof(C) == 8) {
+      const uint64_t u = static_cast<uint64_t>(__double_as_longlong(static_cast<double>(v))) ^
+                         (static_cast<uint64_t>(im & 0x80000000u) << 32);
+      return static_cast<C>(__longlong_as_double(static_cast<long long>(u)));
+    } else {
+      return static_cast<C>(
+          __uint_as_float(__float_as_uint(static_cast<float>(v)) ^ (im & 0x80000000u)));
+    }
+  };
+  // H_rc of an entry: the FP64 pass of sigma_0 reads FP64 H.
+  auto hval = [&](const WideEntry &e, int rc) -> C {
+    if constexpr (X0SRC)
+      return static_cast<C>(c.hg[rc]);
+    else
+      return static_cast<C>(wide_h_value<T>(e.h));
   };
   const WideEntry eab = c.sent[a * N + b];
   const bool offd = a != b;
@@ -1447,8 +1480,8 @@ __device__ __forceinline__ void wide_finish(const WideCtx<T> &c, int a, int b,
     mask &= mask - 1;
     const WideEntry eak = rowA[k];
     const WideEntry ekb = colB[k * N];
-    const C hak = static_cast<C>(eak.h);
-    const C hkb = static_cast<C>(ekb.h);
+    const C hak = hval(eak, a * N + k);
+    const C hkb = hval(ekb, k * N + b);
     const C xkb_r = xre(ekb.re);
     const C xkb_i = xim(ekb.im);
     const C xak_r = xre(eak.re);
@@ -1569,7 +1602,7 @@ __global__ void __launch_bounds__(64 * kWideWaves)
     sent[idx] = WideEntry{static_cast<uint32_t>(ent_re(N, r, c)) * kPlaneBytes,
                           static_cast<uint32_t>(ent_im(N, r, c)) * kPlaneBytes |
                               (r > c ? 0x80000000u : 0u),
-                          Pg[o.h_re + idx]};
+                          wide_h_slot<T>(Pg[o.h_re + idx])};
   }
   for (int idx = tid; idx < N; idx += blockDim.x) {
     uint32_t m = 0;
@@ -1648,6 +1681,7 @@ __global__ void __launch_bounds__(64 * kWideWaves)
                       gmem(static_cast<const T *>(bufs.y)),
                       gmem(static_cast<T *>(bufs.out)),
                       sx0,
+                      Pg + o.h_re,
                       gmem(bufs.y0),
                       gmem(bufs.out0),
                       static_cast<uint32_t>(S),
