@@ -417,8 +417,8 @@ def _small(heom, torch, workloads, stream, reps=5):
     """Small hierarchies, where a stage launch lasts about its launch floor:
     the dimer (15 ADOs, 1000 steps, every step recorded), a 3-site solve with a
     Matsubara term (84 ADOs), a 7-site depth-2 solve (36 ADOs), a 6-site
-    depth-3 solve (84 ADOs, two packed elements x ADOs per thread) and an
-    8-site depth-2 solve (45 ADOs, four per thread on 512 threads), 5000 steps
+    depth-3 solve (84 ADOs) and an 8-site depth-2 solve (45 ADOs), both three
+    packed elements x ADOs per thread on 768 threads, 5000 steps
     with records every 10, each on the default path (the resident kernel:
     every step of a chunk in one launch) and on the stage-per-launch path,
     wall clock per solve (the faster of `reps`), results compared bitwise."""

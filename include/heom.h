@@ -80,8 +80,11 @@ enum {
                                the hierarchy in LDS): FP64, real H, unscaled,
                                and either every instance with the same N <= 8
                                and K+1 <= 2 and at most 2048 packed elements x
-                               ADOs, or N <= 4 and at most 1024 of them;
-                               results are bitwise the same                   */
+                               ADOs (P * ceil(n / 4) <= 512 for P packed
+                               elements and n ADOs; with K+1 = 1 also
+                               P * ceil(n / 3) <= 768, up to 2304), or N <= 4
+                               and at most 1024 of them; results are bitwise
+                               the same                                       */
 };
 /* Flag bits that force tile launch shape s (0 <= s < heom_tile_shape_count())
  * for every tile-kernel group of a call. */

@@ -169,16 +169,32 @@ int resident_lds_bytes(int N, int M, int64_t n_ados, bool fixed) {
 }
 
 // Threads per workgroup of the compile-time resident kernel with R items per
-// thread: 1024 for one or two, 512 for four (the registers of four items).
-int resident_threads(int R) { return R >= 4 ? 512 : 1024; }
+// thread: 1024 for one or two, 768 for three, 512 for four (the registers of
+// the items).
+int resident_threads(int R) { return R >= 4 ? 512 : (R == 3 ? 768 : 1024); }
+
+// Cost of the compile-time resident kernel's LDS accesses for an instance of
+// n ADOs with R items per thread: R passes over the 16-lane groups that hold
+// items, each group that spans two elements weighted 11/8 for its bank
+// conflicts (a count of LDS cycles per access up to a constant).  0 where
+// the instance does not fit the workgroup.
+int64_t resident_fixed_cost(int N, int64_t n_ados, int R) {
+  const int64_t P = static_cast<int64_t>(N) * (N + 1) / 2;
+  const int threads = resident_threads(R);
+  const int64_t W = (n_ados + R - 1) / R;
+  if (R < 1 || n_ados < 1 || P * W > threads) return 0;
+  const int L = fixed_lanes(static_cast<int>(P), static_cast<int>(W), threads);
+  return L % 16 == 0 ? R * P * (L / 16) * 8 : R * ((P * W + 15) / 16) * 11;
+}
 
 // The resident kernel with compile-time N, K+1 and items per thread R, or
-// nullptr where not built (N <= 8, K+1 <= 2, R in {1, 2, 4}).
+// nullptr where not built (N <= 8, K+1 <= 2, 1 <= R <= 4).
 template <int N, int KP>
 const void *resident_fixed_r(int R) {
   switch (R) {
     case 1: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 1, 1024>);
     case 2: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 2, 1024>);
+    case 3: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 3, 768>);
     case 4: return reinterpret_cast<const void *>(&stage_resident_fixed<N, KP, 4, 512>);
     default: return nullptr;
   }

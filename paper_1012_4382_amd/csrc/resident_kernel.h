@@ -341,6 +341,19 @@ __host__ __device__ inline int fixed_lds_bytes(int N, int n) {
   return 3 * n * fixed_ado_bytes(N) + 3 * kScalars * 8;
 }
 
+// Threads of one element in the compile-time kernel, whose P elements each
+// take W items per pass on `threads` threads: W rounded up to a multiple of
+// 16 where that leaves the last wave without items, else W.  An LDS access
+// of 16 bytes per lane serves 16 lanes at a time; lanes of one element read
+// one entry of consecutive ADOs, whose 16-byte offsets (an odd count apart)
+// fall in distinct banks, so a group of 16 lanes that holds one element only
+// has no bank conflict there, where a group that spans two elements mostly
+// has.  The last wave also sums the sink populations of every stage; items
+// there would add that chain to the stage's longest wave.
+__host__ __device__ constexpr int fixed_lanes(int P, int W, int threads) {
+  return P * ((W + 15) / 16 * 16) <= threads - 64 ? (W + 15) / 16 * 16 : W;
+}
+
 struct Cplx {
   double re, im;
 };
@@ -407,11 +420,12 @@ __global__ void __launch_bounds__(THREADS)
   const double tr_l = lane < N ? prm[o.trap + lane] : 0.0;
   const double rc_l = lane < N ? prm[o.rec + lane] : 0.0;
 
-  // This thread's element and items.
+  // This thread's element and items: items j, j + W, ... of element p.
   const int W = (n + R - 1) / R;
-  const bool active = tid < P * W;
-  const int p = active ? tid / W : 0;
-  const int j = active ? tid - p * W : 0;
+  const int L = fixed_lanes(P, W, THREADS);
+  const bool active = tid < P * L && tid % L < W;
+  const int p = active ? tid / L : 0;
+  const int j = active ? tid - p * L : 0;
   const int a = elem_a(N, p), b = elem_b(N, p);
   const bool offd = a != b;
   double hak[N], hkb[N];

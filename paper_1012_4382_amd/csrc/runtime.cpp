@@ -41,7 +41,7 @@ hipError_t launch_snapshot(bool mixed, const InstDesc *descs, int n_inst, int sl
 hipError_t static_scratch(int device, void **ptr);
 int resident_lds_bytes(int N, int M, int64_t n_ados, bool fixed);
 bool resident_fixed_usable(int N, int KP, int R);
-int resident_threads(int R);
+int64_t resident_fixed_cost(int N, int64_t n_ados, int R);
 hipError_t prepare_resident(int N, int KP, int R, int bytes);
 hipError_t launch_resident(int N, int KP, int R, const InstDesc *descs, int n_inst,
                            int64_t step0, int64_t n_steps, int64_t record_every, int slot0,
@@ -447,10 +447,10 @@ constexpr int64_t kResidentChunkSteps = 4096;
 // Where one workgroup runs a stage faster than a stage launch.  The
 // compile-time kernel (every instance of the call with the same N <= 8 and
 // K+1 <= 2) holds each thread's element operands in registers and takes R
-// items (packed element x ADO) per thread: one or two on 1024 threads (two
-// only where that instance needs no scratch memory), else four on 512;
-// measured 1.6-6x faster than stage launches from the dimer to 8 sites at
-// depth 2.  The run-time-N
+// items (packed element x ADO) per thread: one or two on 1024 threads, three
+// on 768, four on 512, each only where that instance needs no scratch
+// memory; measured 1.6-6x faster than stage launches from the dimer to 8
+// sites at depth 2.  The run-time-N
 // kernel, for calls that mix hierarchies, takes one item per thread and few
 // sites (its per-element chain grows with N: the dimer 2.3x faster, 7 sites
 // at depth 2 0.86x).
@@ -470,13 +470,15 @@ struct ResidentPlan {
 // FP64 storage, hierarchies the LDS-tiled kernels run (real H), unscaled and
 // unfiltered, no split, small enough, and no flag that asks for another
 // kernel.  A call whose instances share N and K+1 takes the compile-time
-// kernel, with the fewest items per thread that cover its largest instance.
+// kernel, with the items per thread whose LDS accesses cost least on its
+// costliest instance (more items only where that saves over a tenth: fewer
+// items per thread leave more waves to hide latency with).
 ResidentPlan resident_plan(heom_hierarchy *const *hs, int n, bool mixed, int flags, bool split) {
   const ResidentPlan none;
   if (mixed || split || n < 1) return none;
   if (flags & (HEOM_NO_RESIDENT | HEOM_GENERIC_KERNEL | HEOM_LANE_KERNEL)) return none;
   if (forced_shape(flags) >= 0) return none;
-  int bytes_rt = 0, bytes_fx = 0, R = 1;
+  int bytes_rt = 0, bytes_fx = 0;
   bool same = true, small = true;
   for (int k = 0; k < n; ++k) {
     const heom_hierarchy *h = hs[k];
@@ -489,29 +491,31 @@ ResidentPlan resident_plan(heom_hierarchy *const *hs, int n, bool mixed, int fla
     bytes_fx = std::max(bytes_fx, resident_lds_bytes(h->N, h->M, h->n_ados, true));
     same = same && h->N == hs[0]->N && h->KP == hs[0]->KP;
     small = small && h->N <= kResidentMaxSites && h->n_ados * P <= kResidentMaxItems;
-    int r = 1;
-    while (r <= 2 && P * ((h->n_ados + r - 1) / r) > kResidentMaxItems) ++r;
-    R = std::max(R, r);
-  }
-  // Two items per thread where that instance keeps them in registers, else
-  // four on half the threads (the same number of items).
-  if (R == 2 && hs[0]->N <= kResidentFixedSites && hs[0]->KP <= 2 &&
-      !resident_fixed_usable(hs[0]->N, hs[0]->KP, 2))
-    R = 4;
-  if (R == 4) {
-    for (int k = 0; k < n; ++k) {
-      const int64_t P = static_cast<int64_t>(hs[k]->N) * (hs[k]->N + 1) / 2;
-      if (P * ((hs[k]->n_ados + 3) / 4) > resident_threads(4)) R = kResidentMaxR + 1;
-    }
   }
   ResidentPlan plan;
-  if (same && hs[0]->N <= kResidentFixedSites && hs[0]->KP <= 2 && R <= kResidentMaxR &&
-      bytes_fx <= kResidentMaxLds && resident_fixed_usable(hs[0]->N, hs[0]->KP, R)) {
-    plan.bytes = bytes_fx;
-    plan.N = hs[0]->N;
-    plan.KP = hs[0]->KP;
-    plan.R = R;
-    return plan;
+  if (same && hs[0]->N <= kResidentFixedSites && hs[0]->KP <= 2 && bytes_fx <= kResidentMaxLds) {
+    int64_t best = 0;
+    for (int r = 1; r <= kResidentMaxR; ++r) {
+      int64_t cost = 0;
+      for (int k = 0; k < n; ++k) {
+        const int64_t c = resident_fixed_cost(hs[0]->N, hs[k]->n_ados, r);
+        if (c == 0) {
+          cost = 0;
+          break;
+        }
+        cost = std::max(cost, c);
+      }
+      if (cost == 0 || (plan.R > 0 && 10 * cost >= 9 * best)) continue;
+      if (!resident_fixed_usable(hs[0]->N, hs[0]->KP, r)) continue;
+      plan.R = r;
+      best = cost;
+    }
+    if (plan.R > 0) {
+      plan.bytes = bytes_fx;
+      plan.N = hs[0]->N;
+      plan.KP = hs[0]->KP;
+      return plan;
+    }
   }
   if (small && bytes_rt <= kResidentMaxLds) plan.bytes = bytes_rt;
   return plan;

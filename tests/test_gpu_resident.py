@@ -5,18 +5,20 @@ The resident kernels repeat the tile kernel's operations in its order, so the
 paths must agree bitwise: records, sinks and the full final state.  The
 default ("auto") takes a resident kernel where a run fits one: the
 compile-time kernel where every instance of the call has the same N <= 8 and
-K+1 <= 2 (one, two or four packed elements x ADOs per thread, full matrices
-in LDS), else the run-time-N kernel for batches that mix hierarchies (N <= 4, at
-most 1024 elements x ADOs each); "tiled" forces the stage kernels.  Cases:
-the dimer (15 ADOs), a 3-site hierarchy with sinks and a Matsubara term (84
-ADOs), a 4-site depth-3 hierarchy (35 ADOs), the 7-site FMO model at depth 2
-(36 ADOs), an 8-site depth-1 hierarchy, two items per thread (a 6-site
-depth-3 hierarchy, 84 ADOs, and the dimer at depth 25, 351 ADOs, an odd count
-that leaves the last thread of each element one item), four items per thread
-on 512 threads where two would spill (8 sites at depth 2, 45 ADOs; 3 sites
-with a Matsubara term at depth 4, 210 ADOs, the last group ragged), mixed and
-same-N batches, ring drains over 512 records, runs longer than one resident launch,
-resume, and the efficiency entry point.
+K+1 <= 2 (one to four packed elements x ADOs per thread, full matrices in
+LDS, each element's threads padded to a multiple of 16 where the workgroup
+holds them), else the run-time-N kernel for batches that mix hierarchies
+(N <= 4, at most 1024 elements x ADOs each); "tiled" forces the stage
+kernels.  Cases: the dimer (15 ADOs), a 3-site hierarchy with sinks and a
+Matsubara term (84 ADOs), a 4-site depth-3 hierarchy (35 ADOs), the 7-site
+FMO model at depth 2 (36 ADOs, unpadded), an 8-site depth-1 hierarchy, two
+items per thread (the dimer at depth 25, 351 ADOs, an odd count that leaves
+the last thread of each element one item), three items per thread on 768
+threads (a 6-site depth-3 hierarchy, 84 ADOs; 8 sites at depth 2, 45 ADOs),
+four items per thread on 512 threads where two and three would spill (3
+sites with a Matsubara term at depth 4, 210 ADOs, the last group ragged),
+mixed and same-N batches, ring drains over 512 records, runs longer than one
+resident launch, resume, and the efficiency entry point.
 """
 import sys
 import time
@@ -81,9 +83,9 @@ CASES = {
     "3site_K1_depth3": _three_site_matsubara,
     "fmo_table1_depth2": lambda: (workloads.fmo_table1(), 2, workloads.site_state(7, 1)),
     "8site_depth1": lambda: _n_site(8, 1),
-    "6site_depth3_two_items": lambda: _n_site(6, 3, seed=1),
+    "6site_depth3_three_items": lambda: _n_site(6, 3, seed=1),
     "dimer_depth25_ragged": lambda: (workloads.dimer()["system"], 25, workloads.dimer()["rho0"]),
-    "8site_depth2_four_items": lambda: _n_site(8, 2, seed=2),
+    "8site_depth2_three_items": lambda: _n_site(8, 2, seed=2),
     "3site_K1_depth4_four_items": lambda: _n_site(3, 4, seed=3, K=1),
 }
 
