@@ -35,6 +35,21 @@ __device__ __forceinline__ void res_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// wave_sum's lane-0 result where lanes 0 .. N-1 (N <= 8) hold term(0 .. N-1)
+// and the other lanes zero, as one lane's additions in the butterfly's
+// order: offsets 32, 16 and 8 add zeros (which only turn -0 into +0), then
+// 4, 2 and 1 pair the sites.  Bitwise equal to wave_sum, without its chain
+// of dependent shuffles (the scalar wave's longest chain in a stage of the
+// compile-time kernel).
+template <typename Term>
+__device__ __forceinline__ double site_sum(int N, Term term) {
+#pragma clang fp contract(off)
+  double w[8];
+#pragma unroll
+  for (int l = 0; l < 8; ++l) w[l] = l < N ? term(l) + 0.0 : 0.0;
+  return ((w[0] + w[4]) + (w[2] + w[6])) + ((w[1] + w[5]) + (w[3] + w[7]));
+}
+
 // LDS layout of the resident kernel (byte offsets, 16-byte aligned regions)
 // for an instance of n ADOs: the state Y and the stage buffers A and B as
 // [N*N + 1][n] planes (plane N*N is zero: the imaginary part of a diagonal
@@ -233,7 +248,9 @@ __device__ __forceinline__ ResidentStages resident_stages(const ResidentView &v,
 }
 
 // The scalar part of stage st, on one whole wave: scalar_update_wave's
-// operations with the sink rates from LDS.
+// operations with the sink rates from LDS.  (Each lane forming every site's
+// term and summing them as site_sum does measured slower here than the
+// shuffles: with N known at run time that is 3N guarded LDS reads a lane.)
 __device__ __forceinline__ void resident_scalars(const ResidentView &v, const ResidentStages &g,
                                                  int st, int N, int n, int lane) {
 #pragma clang fp contract(off)
@@ -337,8 +354,10 @@ __global__ void __launch_bounds__(kResidentThreads)
 __host__ __device__ constexpr int fixed_ado_bytes(int N) {
   return (N * N + (N % 2 == 0 ? 1 : 0)) * 16;
 }
+// The three buffers of n ADOs, the scalars of each, and the (trap,
+// recombination) rate pair of each site.
 __host__ __device__ inline int fixed_lds_bytes(int N, int n) {
-  return 3 * n * fixed_ado_bytes(N) + 3 * kScalars * 8;
+  return 3 * n * fixed_ado_bytes(N) + 3 * kScalars * 8 + N * 16;
 }
 
 // Threads of one element in the compile-time kernel, whose P elements each
@@ -382,6 +401,7 @@ __global__ void __launch_bounds__(THREADS)
     stage_resident_fixed(const InstDesc *__restrict__ descs, int64_t step0, int64_t n_steps,
                          int64_t record_every, int slot0, double dt) {
 #pragma clang fp contract(off)
+  static_assert(N >= 1 && N <= 8, "site_sum covers up to 8 sites");
   constexpr int N2 = N * N, P = N * (N + 1) / 2, M = N * KP;
   constexpr uint32_t SD = fixed_ado_bytes(N);
   extern __shared__ __align__(16) char res_smem[];
@@ -394,6 +414,9 @@ __global__ void __launch_bounds__(THREADS)
   char *const buf1 = res_smem + n * SD;
   char *const buf2 = res_smem + 2 * n * SD;
   double *const sc = reinterpret_cast<double *>(res_smem + 3 * n * SD);  // [Y, A, B][kScalars]
+  // (trap, recombination) rates of each site, read by the scalar wave every
+  // stage (from LDS, so that no register holds them across the steps).
+  char *const rates = res_smem + 3 * n * SD + 3 * kScalars * 8;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
 
@@ -416,9 +439,7 @@ __global__ void __launch_bounds__(THREADS)
     reinterpret_cast<double *>(buf1)[q] = 0.0;
   for (int q = tid; q < 3 * kScalars; q += THREADS)
     sc[q] = q < kScalars ? d.sc_y[q] : 0.0;
-  // Sink rates of site `lane` for the scalar wave.
-  const double tr_l = lane < N ? prm[o.trap + lane] : 0.0;
-  const double rc_l = lane < N ? prm[o.rec + lane] : 0.0;
+  if (tid < N) lds_put(rates, tid * 16, prm[o.trap + tid], prm[o.rec + tid]);
 
   // This thread's element and items: items j, j + W, ... of element p.
   const int W = (n + R - 1) / R;
@@ -487,15 +508,18 @@ __global__ void __launch_bounds__(THREADS)
       const int sout = st == 3 ? 0 : (st == 1 ? 2 : 1);
       const double coef = coefs[st];
       if (wave == THREADS / 64 - 1) {
-        // The scalar part (scalar_update_wave's operations).
-        double ft = 0.0, fr = 0.0;
-        if (lane < N) {
-          const double pop = lds_c(xb, static_cast<uint32_t>(lane * N + lane) * 16u).re;
-          ft = fmad(tr_l, pop, ft);
-          fr = fmad(rc_l, pop, fr);
+        // The scalar part: scalar_update_wave's operations, every site's
+        // flux term in each lane (broadcast LDS reads) and lane 0's sum.
+        double vt[N], vr[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+          const double pop = lds_c(xb, static_cast<uint32_t>(a * N + a) * 16u).re;
+          const Cplx rate = lds_c(rates, a * 16);
+          vt[a] = fmad(rate.re, pop, 0.0);
+          vr[a] = fmad(rate.im, pop, 0.0);
         }
-        ft = wave_sum(ft);
-        fr = wave_sum(fr);
+        const double ft = site_sum(N, [&](int a) { return vt[a]; });
+        const double fr = site_sum(N, [&](int a) { return vr[a]; });
         if (lane == 0) {
           const double xq = sc[sin_ * kScalars];
           const double y_t = sc[0], y_r = sc[1], y_q = sc[2];
