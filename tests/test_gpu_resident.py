@@ -17,8 +17,9 @@ the last thread of each element one item), three items per thread on 768
 threads (a 6-site depth-3 hierarchy, 84 ADOs; 8 sites at depth 2, 45 ADOs),
 four items per thread on 512 threads where two and three would spill (3
 sites with a Matsubara term at depth 4, 210 ADOs, the last group ragged),
-mixed and same-N batches, ring drains over 512 records, runs longer than one
-resident launch, resume, and the efficiency entry point.
+mixed and same-N batches (one of 8-site instances of depths 2, 1 and 2 on three
+items per thread), ring drains over 512 records, runs longer than one resident
+launch, resume, and the efficiency entry point.
 """
 import sys
 import time
@@ -162,6 +163,29 @@ def test_resident_fixed_batch_ring_drains_and_chunks():
         h.close()
 
 
+def test_resident_fixed_three_items_ragged_batch():
+    """A batch of 8-site instances of depths 2, 1 and 2 (the compile-time
+    kernel with three items per thread on 768 threads, chosen for the costlier
+    depth-2 instances; each element's threads padded to 16, so the depth-1
+    instance, 9 ADOs, leaves 13 of every 16 threads without items), 600
+    records, against the stage launches bitwise and the oracle."""
+    batch = [_n_site(8, 2, seed=4), _n_site(8, 1, seed=5), _n_site(8, 2, seed=6)]
+    hs = [heom.Hierarchy(s, d) for s, d, _ in batch]
+    r0 = [r for _, _, r in batch]
+    _say("case: compile-time resident batch, 8 sites depths 2/1/2, 600 steps, every step")
+    rho, sinks, _ = heom.propagate_batch(hs, r0, 1.0, 600, record_every=1)
+    rho_t, sinks_t, _ = heom.propagate_batch(hs, r0, 1.0, 600, record_every=1, kernel="tiled")
+    for k in range(len(hs)):
+        assert np.array_equal(rho[k], rho_t[k]), k
+    assert np.array_equal(np.asarray(sinks), np.asarray(sinks_t))
+    for k in (0, 1):
+        sys_, depth, _ = batch[k]
+        ref = oracle.propagate(sys_, depth, r0[k], 1.0, 600, record_every=100)
+        assert _rel(rho[k][::100], ref["rho"]) <= FP64_TOL, k
+    for h in hs:
+        h.close()
+
+
 def test_resident_resume_and_efficiency():
     sys_, depth, rho0 = _four_site(3)
     h = heom.Hierarchy(sys_, depth)
@@ -181,9 +205,10 @@ def test_resident_resume_and_efficiency():
 
 def test_resident_is_faster_for_the_dimer():
     """The point of the resident kernel: the dimer's steps in a few launches
-    instead of four stage launches each (the compile-time form measured 5.6x
-    over 5000 steps with records every 10, the run-time form 2.0x; here 10000
-    steps, workspace and stream reused, the best of three calls, bar 1.5x)."""
+    instead of four stage launches each (the compile-time form measured 9.6x
+    on 1000 steps with every step recorded, the run-time form 2.0x over 5000
+    steps with records every 10; here 10000 steps, workspace and stream
+    reused, the best of three calls, bar 1.5x)."""
     import torch
 
     w = workloads.dimer()
