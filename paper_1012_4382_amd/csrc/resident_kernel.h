@@ -309,7 +309,11 @@ __global__ void __launch_bounds__(kResidentThreads)
   resident_load(d, v, N, M, n, tid);
   const ResidentStages g = resident_stages(v, dt);
   const int wave = tid >> 6, lane = tid & 63;
+  // This thread's item (at most one: the host keeps P * n <= the threads).
+  const bool has_item = tid < P * n;
+  const int ip = has_item ? tid / n : 0, ii = has_item ? tid % n : 0;
   int slot = slot0;
+  int64_t to_rec = record_every > 0 ? record_every - step0 % record_every : -1;
   for (int64_t s = 0; s < n_steps; ++s) {
     for (int st = 0; st < 4; ++st) {
       // The scalars on the last wave (the element items fill the first
@@ -317,14 +321,15 @@ __global__ void __launch_bounds__(kResidentThreads)
       if (wave == kResidentThreads / 64 - 1) resident_scalars(v, g, st, N, n, lane);
       const ResidentCtx c{N,    d.KP, n,    g.xin[st], v.Y,  g.xout[st], v.H, v.hg,
                           v.dl, v.cr, v.ci, v.damp,    v.up, v.dn,       v.occ};
-      for (int q = tid; q < P * n; q += kResidentThreads) {
-        const int p = q / n, i = q % n;
-        resident_element(c, v.pa[p], v.pb[p], i, g.coef[st]);
-      }
+      if (has_item) resident_element(c, v.pa[ip], v.pb[ip], ii, g.coef[st]);
       res_barrier();
     }
-    if (record_every > 0 && (step0 + s + 1) % record_every == 0)
+    // Steps until the next recorded one, counted down (no 64-bit remainder
+    // per step).
+    if (--to_rec == 0) {
+      to_rec = record_every;
       resident_record(d, v, N, n, slot++, tid);
+    }
   }
   resident_store(d, v, N, n, tid);
 }
@@ -499,6 +504,7 @@ __global__ void __launch_bounds__(THREADS)
   // Stage buffers as in the stage launches: Y -> A -> B -> A -> Y.
   const double coefs[4] = {dt / 4.0, dt / 3.0, dt / 2.0, dt};
   int slot = slot0;
+  int64_t to_rec = record_every > 0 ? record_every - step0 % record_every : -1;
   for (int64_t s = 0; s < n_steps; ++s) {
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -570,7 +576,10 @@ __global__ void __launch_bounds__(THREADS)
       }
       res_barrier();
     }
-    if (record_every > 0 && (step0 + s + 1) % record_every == 0) {
+    // Steps until the next recorded one, counted down (no 64-bit remainder
+    // per step).
+    if (--to_rec == 0) {
+      to_rec = record_every;
       // sigma_0 (packed) and the sink scalars into the history ring.
       double *h = d.hist + static_cast<int64_t>(slot) * (N2 + kScalars);
       for (int e = tid; e < N2; e += THREADS) {

@@ -454,7 +454,7 @@ constexpr int64_t kResidentChunkSteps = 4096;
 // kernel, for calls that mix hierarchies, takes one item per thread and few
 // sites (its per-element chain grows with N: the dimer 2.3x faster, 7 sites
 // at depth 2 0.86x).
-constexpr int64_t kResidentMaxItems = 1024;
+constexpr int64_t kResidentMaxItems = 1024;  // the run-time kernel's threads: one item each
 constexpr int kResidentMaxSites = 4;
 constexpr int kResidentFixedSites = 8;
 constexpr int kResidentMaxR = 4;
