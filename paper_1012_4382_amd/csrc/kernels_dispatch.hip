@@ -222,13 +222,24 @@ const void *resident_kernel(int N, int KP, int R) {
 
 // Whether the compile-time resident kernel for (N, K+1, R) is built and
 // keeps every value in registers (no scratch memory: a spilled operand would
-// cost a memory round trip per stage).
+// cost a memory round trip per stage).  A property of the code object, so
+// each instance is asked once per process (a failed query is not kept).
 bool resident_fixed_usable(int N, int KP, int R) {
   const void *k = R > 0 ? resident_kernel(N, KP, R) : nullptr;
   if (!k) return false;
+  static std::mutex mu;
+  static std::map<const void *, bool> known;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = known.find(k);
+    if (it != known.end()) return it->second;
+  }
   hipFuncAttributes attr{};
   if (hipFuncGetAttributes(&attr, k) != hipSuccess) return false;
-  return attr.localSizeBytes == 0;
+  const bool usable = attr.localSizeBytes == 0;
+  std::lock_guard<std::mutex> lock(mu);
+  known[k] = usable;
+  return usable;
 }
 
 // Lets the resident kernel (R = 0: run-time N; else the compile-time
